@@ -1,0 +1,192 @@
+/*
+ * rbns.h -- C ABI of the MI355X (gfx950) online solver for the velocity-only reduced-basis
+ * Navier-Stokes method (Fonn, van Brummelen, Kvamsdal, Rasheed: "Fast divergence-conforming
+ * reduced basis methods for steady Navier-Stokes flow").
+ *
+ * The online stage, per parameter mu (Sections 2.2, 2.4, 3.4, 3.5, 4.1 of the paper):
+ *   solve  F(u) = A(mu) u + C(mu)(u, u) - f(mu) = 0   (velocity-only system, eqn velonly)
+ *   with   A(mu) = sum_q theta^a_q(mu) A_q,
+ *          C(mu)(v, w)_i = sum_q theta^c_q(mu) sum_jk C_q[i][j][k] v_j w_k,
+ *          f(mu) = sum_q theta^f_q(mu) f_q                (affine representation, eqns split-*)
+ *   by Newton's method with the Jacobian assembled from the precomputed third-order tensors
+ *          J = A(mu) + sum_q theta^c_q sum_k (C_q[:, :, k] + C_q[:, k, :]) u_k    (Section 3.5)
+ *   and a dense pivoted LU solve per step; then recover the pressure a posteriori
+ *          B(mu) p = f_s(mu) - A_sv(mu) u - C_sv(mu)(u, u)          (eqns sup-vvar, blocksolve-2).
+ *
+ * Conventions for every entry point:
+ *   - All matrices are row-major (C order), FP64 on the host side of rb_load_tensors.
+ *   - Per-request arrays are DEVICE pointers owned by the caller; calls enqueue work on the
+ *     given HIP stream (hipStream_t passed as void*, NULL = the null stream) and return
+ *     without synchronising. Outputs are valid once that stream has completed.
+ *   - Calls on one context that share a stream are ordered by it; the library keeps one
+ *     workspace per stream, so calls on different streams may overlap.
+ *   - Return value: RB_OK, or a negative call-level error, in which case nothing was
+ *     enqueued and rb_last_error() describes the failure (thread-local message).
+ *   - Per-request outcomes are reported in status arrays (RB_ST_*), never as call errors.
+ */
+#ifndef RBNS_H
+#define RBNS_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* call-level return codes */
+#define RB_OK             0
+#define RB_E_INVAL       -1   /* bad argument: NULL pointer, size out of range, unknown set  */
+#define RB_E_NOMEM       -2   /* the request exceeds the context's HBM budget, or hipMalloc */
+#define RB_E_DEVICE      -3   /* a HIP runtime call failed                                   */
+#define RB_E_STATE       -4   /* context not usable (destroyed, wrong device)                */
+#define RB_E_UNSUPPORTED -5   /* valid request this build does not implement                 */
+
+/* per-request status codes */
+#define RB_ST_CONVERGED  0    /* update below tolerance                                      */
+#define RB_ST_MAXIT      1    /* iteration limit reached; the last iterate is returned       */
+#define RB_ST_SINGULAR   2    /* zero pivot in the Newton (or pressure) system               */
+#define RB_ST_NONFINITE  3    /* NaN or Inf in an operand, update or iterate                 */
+#define RB_ST_BADN       4    /* basis size out of range for the loaded set                  */
+
+/* arithmetic of the Newton iteration */
+#define RB_PREC_F64      0    /* FP64 tensors, FP64 MFMA contraction, FP64 LU                */
+#define RB_PREC_F32      1    /* FP32 contraction + FP32 LU, then FP64 residual refinement   */
+
+typedef struct rb_ctx rb_ctx;
+
+/*
+ * Reduced operators of one parameterised model (host pointers, FP64, copied on load).
+ * Sizes are the stored maxima; bases are nested, so a solve at basis size N <= N uses the
+ * leading N x N (x N) blocks. Index meaning (row index = test function, as in a Galerkin
+ * matrix; paper eqn tensor writes C^i_{jkl} = c_i(u_j, u_k, u_l), i.e. C_q[l][j][k] here):
+ *   A   [Q][N][N]        A_q[i][j]      = a_q(phi_j, phi_i)
+ *   C   [Qc][N][N][N]    C_q[i][j][k]   = c_q(phi_j, phi_k, phi_i)   (j advects, k advected)
+ *   F   [Qf][N]          f_q[i]         = d_q(phi_i)
+ *   H   [N][N] or NULL   Gram matrix of the norm used by the stopping test (the paper uses the
+ *                        H^1 seminorm, Section 6); NULL selects the Euclidean norm.
+ * Optional pressure recovery data (Np = 0 disables it):
+ *   Bp  [Qb][Np][Np]     B_q[i][j]      = b_q(p_j, s_i)   (s_i = supremizers, Section 3.4)
+ *   Asv [Q][Np][N]       A_sv,q[i][j]   = a_q(phi_j, s_i)
+ *   Csv [Qc][Np][N][N]   C_sv,q[i][j][k]= c_q(phi_j, phi_k, s_i)
+ *   Fs  [Qf][Np]         f_s,q[i]       = d_q(s_i)
+ */
+typedef struct {
+    int N, Q, Qc, Qf;
+    const double *A, *C, *F, *H;
+    int Np, Qb;
+    const double *Bp, *Asv, *Csv, *Fs;
+} rb_tensors_desc;
+
+typedef struct {
+    double tol;          /* stop when ||delta|| <= tol * ||u|| (norm given by H)           */
+    int max_iter;        /* Newton iteration limit (>= 1)                                    */
+    int precision;       /* RB_PREC_*                                                        */
+    int refine_steps;    /* RB_PREC_F32 only: FP64-residual refinement steps after the FP32
+                            iteration has stagnated (>= 1)                                   */
+} rb_solve_opts;
+
+/* Size limits of this build (the LU keeps one system row per lane of a 64-wide wavefront). */
+#define RB_MAX_N   64
+#define RB_MAX_NP  64
+#define RB_MAX_Q   12
+#define RB_MAX_QC   4
+#define RB_MAX_QF   2
+#define RB_MAX_QB   2
+
+/*
+ * rb_create: make a context on HIP device `device`. hbm_budget_bytes caps the device memory
+ * the context may hold (resident tensors + workspaces); 0 means no cap.
+ * Errors: RB_E_INVAL (out == NULL, bad device), RB_E_DEVICE.
+ */
+int rb_create(int device, size_t hbm_budget_bytes, rb_ctx **out);
+
+/* rb_destroy: free every device buffer of the context. Pending work must have completed. */
+int rb_destroy(rb_ctx *ctx);
+
+/* rb_last_error: message for the last failing call on this thread ("" if none). */
+const char *rb_last_error(void);
+
+/* rb_hbm_used: bytes of device memory the context currently holds. */
+size_t rb_hbm_used(const rb_ctx *ctx);
+
+/*
+ * rb_load_tensors: copy a model's reduced operators to the device (FP64, plus the packed
+ * contraction operands built from them) and return its set id. The caller may free the host
+ * arrays on return. Synchronous.
+ * Errors: RB_E_INVAL (NULL pointer, sizes out of range), RB_E_NOMEM (over budget),
+ * RB_E_DEVICE.
+ */
+int rb_load_tensors(rb_ctx *ctx, const rb_tensors_desc *desc, int *set_id_out);
+
+/*
+ * rb_theta: evaluate the parameter functions of the loaded model's affine expansion for B
+ * parameters mu[b] = (alpha [rad], Re) (device, [B][2]). Writes theta_a [B][Q],
+ * theta_c [B][Qc], theta_f [B][Qf] and, if the set has pressure data and theta_b != NULL,
+ * theta_b [B][Qb] (all device). Families (trigonometric / polynomial in alpha, viscous 1/Re):
+ *   theta_a = first Q of (1/Re, cos a, sin a, a, a^2, a^3, cos 2a, sin 2a, 1 - cos a, a^4,
+ *             a cos a, a sin a);  theta_c = first Qc of (1, cos a, sin a, a);
+ *   theta_f = (1) if Qf = 1, else (cos a, sin a);  theta_b = (1) if Qb = 1, else (1, a).
+ * Errors: RB_E_INVAL.
+ */
+int rb_theta(rb_ctx *ctx, int set, int B, const double *mu, double *theta_a, double *theta_c,
+             double *theta_f, double *theta_b, void *hip_stream);
+
+/*
+ * rb_solve_batch: B independent reduced Newton solves at one basis size N (1 <= N <= the
+ * set's N). Device inputs: theta_a [B][Q], theta_c [B][Qc], and either theta_f [B][Qf] or
+ * f_override [B][ldu] (right-hand sides replacing f(mu), e.g. for manufactured solutions);
+ * u0 [B][ldu] initial iterates or NULL (zero: the first step is then the Stokes solve).
+ * Device outputs: u [B][ldu] (entries >= N are set to 0), iters [B] (Newton updates applied),
+ * status [B] (RB_ST_*). ldu >= N is the row stride of u0 / f_override / u.
+ * opts == NULL selects tol 1e-12, max_iter 10, RB_PREC_F64.
+ * Errors: RB_E_INVAL (NULL, B < 0, N or ldu out of range, bad opts), RB_E_NOMEM,
+ * RB_E_UNSUPPORTED, RB_E_DEVICE. B == 0 is a no-op.
+ */
+int rb_solve_batch(rb_ctx *ctx, int set, int B, int N, int ldu, const double *theta_a,
+                   const double *theta_c, const double *theta_f, const double *f_override,
+                   const double *u0, const rb_solve_opts *opts, double *u, int *iters,
+                   int *status, void *hip_stream);
+
+/*
+ * rb_solve_uneven: like rb_solve_batch, but each request b has its own basis size
+ * N[b] (device int [B]); rows of u0 / f_override / u have stride ldu >= the set's N.
+ * Requests are grouped by basis size on the device and processed in one persistent launch
+ * whose workgroups take tiles of same-size requests from a device work queue. Requests with
+ * N[b] outside [1, set N] get status RB_ST_BADN.
+ * Errors: as rb_solve_batch.
+ */
+int rb_solve_uneven(rb_ctx *ctx, int set, int B, const int *N, int ldu, const double *theta_a,
+                    const double *theta_c, const double *theta_f, const double *f_override,
+                    const double *u0, const rb_solve_opts *opts, double *u, int *iters,
+                    int *status, void *hip_stream);
+
+/*
+ * rb_recover_pressure: a posteriori pressure for B velocity solutions at basis size N and
+ * pressure size Np (<= the set's Np), from eqn sup-vvar with the supremizers as test space:
+ *   B(mu) p = f_s(mu) - A_sv(mu) u - C_sv(mu)(u, u),   B(mu) = sum_q theta^b_q B_q.
+ * Device inputs: theta_a, theta_c, theta_f as for rb_solve_batch, theta_b [B][Qb], u [B][ldu].
+ * Device outputs: p [B][ldp] (entries >= Np set to 0), status [B] (RB_ST_CONVERGED on
+ * success, RB_ST_SINGULAR / RB_ST_NONFINITE otherwise).
+ * Errors: RB_E_INVAL (no pressure data, sizes), RB_E_NOMEM, RB_E_DEVICE.
+ */
+int rb_recover_pressure(rb_ctx *ctx, int set, int B, int N, int Np, int ldu, int ldp,
+                        const double *theta_a, const double *theta_c, const double *theta_f,
+                        const double *theta_b, const double *u, double *p, int *status,
+                        void *hip_stream);
+
+/*
+ * Kernel timing for measurement (used by the benchmark): while enabled, every launch of the
+ * kernel families "jacobian" (MFMA Jacobian + residual contraction), "lu" (pivoted LU solve +
+ * update) and "pressure" (pressure recovery) is bracketed by HIP events recorded on the
+ * stream it is launched on. rb_timing_read waits for the recorded events of one family,
+ * returns their summed duration (ms) and launch count, and forgets them.
+ * Errors: RB_E_INVAL (unknown family), RB_E_DEVICE.
+ */
+int rb_timing_enable(rb_ctx *ctx, int enable);
+int rb_timing_read(rb_ctx *ctx, const char *family, double *total_ms, int *launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RBNS_H */

@@ -1,0 +1,264 @@
+"""ctypes binding of librbns.so (the C ABI in include/rbns.h).
+
+Argument marshalling only: every step of the online solve runs in the HIP library. PyTorch
+provides device memory (tensors) and the current HIP stream; nothing here computes on the
+host. If the shared library is missing the import of this module's functions fails loudly:
+there is no CPU fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librbns.so")
+
+RB_OK, RB_E_INVAL, RB_E_NOMEM, RB_E_DEVICE, RB_E_STATE, RB_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
+RB_ST_CONVERGED, RB_ST_MAXIT, RB_ST_SINGULAR, RB_ST_NONFINITE, RB_ST_BADN = 0, 1, 2, 3, 4
+RB_PREC_F64, RB_PREC_F32 = 0, 1
+
+EXPORTED = ("rb_create", "rb_destroy", "rb_last_error", "rb_hbm_used", "rb_load_tensors",
+            "rb_theta", "rb_solve_batch", "rb_solve_uneven", "rb_recover_pressure",
+            "rb_timing_enable", "rb_timing_read")
+
+_dp = ct.POINTER(ct.c_double)
+_vp = ct.c_void_p
+
+
+class RbError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"rbns error {code}: {msg}")
+        self.code = code
+
+
+class TensorsDesc(ct.Structure):
+    _fields_ = [("N", ct.c_int), ("Q", ct.c_int), ("Qc", ct.c_int), ("Qf", ct.c_int),
+                ("A", _dp), ("C", _dp), ("F", _dp), ("H", _dp),
+                ("Np", ct.c_int), ("Qb", ct.c_int),
+                ("Bp", _dp), ("Asv", _dp), ("Csv", _dp), ("Fs", _dp)]
+
+
+class SolveOpts(ct.Structure):
+    _fields_ = [("tol", ct.c_double), ("max_iter", ct.c_int), ("precision", ct.c_int),
+                ("refine_steps", ct.c_int)]
+
+
+_lib = None
+
+
+def load(path=None):
+    """Load librbns.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = path or LIB_PATH
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} not found: build it with `python -m paper_1807_11866_amd.build`"
+                           " (there is no CPU fallback)")
+    lib = ct.CDLL(path)
+    lib.rb_create.argtypes = [ct.c_int, ct.c_size_t, ct.POINTER(_vp)]
+    lib.rb_destroy.argtypes = [_vp]
+    lib.rb_last_error.restype = ct.c_char_p
+    lib.rb_hbm_used.argtypes = [_vp]
+    lib.rb_hbm_used.restype = ct.c_size_t
+    lib.rb_load_tensors.argtypes = [_vp, ct.POINTER(TensorsDesc), ct.POINTER(ct.c_int)]
+    lib.rb_theta.argtypes = [_vp, ct.c_int, ct.c_int] + [_vp] * 5 + [_vp]
+    lib.rb_solve_batch.argtypes = ([_vp, ct.c_int, ct.c_int, ct.c_int, ct.c_int] + [_vp] * 5 +
+                                   [ct.POINTER(SolveOpts)] + [_vp] * 3 + [_vp])
+    lib.rb_solve_uneven.argtypes = ([_vp, ct.c_int, ct.c_int, _vp, ct.c_int] + [_vp] * 5 +
+                                    [ct.POINTER(SolveOpts)] + [_vp] * 3 + [_vp])
+    lib.rb_recover_pressure.argtypes = ([_vp] + [ct.c_int] * 6 + [_vp] * 7 + [_vp])
+    lib.rb_timing_enable.argtypes = [_vp, ct.c_int]
+    lib.rb_timing_read.argtypes = [_vp, ct.c_char_p, ct.POINTER(ct.c_double),
+                                   ct.POINTER(ct.c_int)]
+    for fn in EXPORTED:
+        if fn not in ("rb_last_error", "rb_hbm_used"):
+            getattr(lib, fn).restype = ct.c_int
+    _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc != RB_OK:
+        raise RbError(rc, load().rb_last_error().decode())
+    return rc
+
+
+def _ptr(t):
+    """Device (or host) address of a torch tensor / numpy array, or None."""
+    if t is None:
+        return None
+    if hasattr(t, "data_ptr"):
+        return ct.c_void_p(t.data_ptr())
+    return ct.c_void_p(t.ctypes.data)
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ct.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if hasattr(stream, "cuda_stream"):
+        return ct.c_void_p(stream.cuda_stream)
+    return ct.c_void_p(stream)
+
+
+# ---------------------------------------------------------------- thin C mirrors ---------
+
+def rb_create(device=0, hbm_budget_bytes=0):
+    ctx = _vp()
+    _check(load().rb_create(int(device), int(hbm_budget_bytes), ct.byref(ctx)))
+    return ctx
+
+
+def rb_destroy(ctx):
+    _check(load().rb_destroy(ctx))
+
+
+def rb_hbm_used(ctx):
+    return load().rb_hbm_used(ctx)
+
+
+def rb_load_tensors(ctx, ts):
+    """Copy a tensor set (numpy FP64 arrays, see rbinputs.TensorSet) to the device."""
+    import numpy as np
+
+    keep = {}
+
+    def p(name):
+        a = getattr(ts, name, None)
+        if a is None:
+            return None
+        a = np.ascontiguousarray(a, dtype=np.float64)
+        keep[name] = a
+        return a.ctypes.data_as(_dp)
+
+    npr = int(getattr(ts, "Np", 0) or 0)
+    d = TensorsDesc(int(ts.N), int(ts.Q), int(ts.Qc), int(ts.Qf), p("A"), p("C"), p("F"),
+                    p("H"), npr, int(getattr(ts, "Qb", 1) or 1),
+                    p("Bp") if npr else None, p("Asv") if npr else None,
+                    p("Csv") if npr else None, p("Fs") if npr else None)
+    sid = ct.c_int(-1)
+    _check(load().rb_load_tensors(ctx, ct.byref(d), ct.byref(sid)))
+    return sid.value
+
+
+def rb_theta(ctx, set_id, B, mu, theta_a, theta_c, theta_f, theta_b=None, stream=None):
+    _check(load().rb_theta(ctx, set_id, int(B), _ptr(mu), _ptr(theta_a), _ptr(theta_c),
+                           _ptr(theta_f), _ptr(theta_b), _stream(stream)))
+
+
+def make_opts(tol=1e-12, max_iter=10, precision=RB_PREC_F64, refine_steps=1):
+    return SolveOpts(float(tol), int(max_iter), int(precision), int(refine_steps))
+
+
+def rb_solve_batch(ctx, set_id, B, N, ldu, theta_a, theta_c, theta_f, f_override, u0, opts,
+                   u, iters, status, stream=None):
+    _check(load().rb_solve_batch(ctx, set_id, int(B), int(N), int(ldu), _ptr(theta_a),
+                                 _ptr(theta_c), _ptr(theta_f), _ptr(f_override), _ptr(u0),
+                                 ct.byref(opts) if opts is not None else None, _ptr(u),
+                                 _ptr(iters), _ptr(status), _stream(stream)))
+
+
+def rb_solve_uneven(ctx, set_id, B, N, ldu, theta_a, theta_c, theta_f, f_override, u0, opts,
+                    u, iters, status, stream=None):
+    _check(load().rb_solve_uneven(ctx, set_id, int(B), _ptr(N), int(ldu), _ptr(theta_a),
+                                  _ptr(theta_c), _ptr(theta_f), _ptr(f_override), _ptr(u0),
+                                  ct.byref(opts) if opts is not None else None, _ptr(u),
+                                  _ptr(iters), _ptr(status), _stream(stream)))
+
+
+def rb_recover_pressure(ctx, set_id, B, N, Np, ldu, ldp, theta_a, theta_c, theta_f, theta_b,
+                        u, p, status, stream=None):
+    _check(load().rb_recover_pressure(ctx, set_id, int(B), int(N), int(Np), int(ldu),
+                                      int(ldp), _ptr(theta_a), _ptr(theta_c), _ptr(theta_f),
+                                      _ptr(theta_b), _ptr(u), _ptr(p), _ptr(status),
+                                      _stream(stream)))
+
+
+def rb_timing_enable(ctx, enable=True):
+    _check(load().rb_timing_enable(ctx, int(bool(enable))))
+
+
+def rb_timing_read(ctx, family):
+    """(total milliseconds, launches) of the timed launches of one kernel family."""
+    ms = ct.c_double(0.0)
+    n = ct.c_int(0)
+    _check(load().rb_timing_read(ctx, family.encode(), ct.byref(ms), ct.byref(n)))
+    return ms.value, n.value
+
+
+# ---------------------------------------------------------------- convenience ------------
+
+class Solver:
+    """One context + one loaded tensor set, with torch-allocated per-call buffers."""
+
+    def __init__(self, ts, device=0, hbm_budget_bytes=0):
+        import torch
+
+        self.torch = torch
+        self.dev = torch.device("cuda", device)
+        self.ctx = rb_create(device, hbm_budget_bytes)
+        self.set = rb_load_tensors(self.ctx, ts)
+        self.N, self.Q, self.Qc, self.Qf = ts.N, ts.Q, ts.Qc, ts.Qf
+        self.Np, self.Qb = int(getattr(ts, "Np", 0) or 0), int(getattr(ts, "Qb", 1) or 1)
+
+    def close(self):
+        if self.ctx:
+            rb_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def theta(self, mu, stream=None):
+        t = self.torch
+        B = mu.shape[0]
+        f64 = dict(dtype=t.float64, device=self.dev)
+        th = dict(ta=t.empty(B, self.Q, **f64), tc=t.empty(B, self.Qc, **f64),
+                  tf=t.empty(B, self.Qf, **f64),
+                  tb=t.empty(B, self.Qb, **f64) if self.Np else None)
+        rb_theta(self.ctx, self.set, B, mu, th["ta"], th["tc"], th["tf"], th["tb"], stream)
+        return th
+
+    def solve(self, th, N=None, f_override=None, u0=None, tol=1e-12, max_iter=10,
+              precision=RB_PREC_F64, refine_steps=1, out=None, stream=None):
+        t = self.torch
+        N = self.N if N is None else N
+        B = th["ta"].shape[0]
+        if out is None:
+            out = dict(u=t.empty(B, self.N, dtype=t.float64, device=self.dev),
+                       iters=t.empty(B, dtype=t.int32, device=self.dev),
+                       status=t.empty(B, dtype=t.int32, device=self.dev))
+        opts = make_opts(tol, max_iter, precision, refine_steps)
+        rb_solve_batch(self.ctx, self.set, B, N, self.N, th["ta"], th["tc"], th["tf"],
+                       f_override, u0, opts, out["u"], out["iters"], out["status"], stream)
+        return out
+
+    def solve_uneven(self, th, Nreq, f_override=None, u0=None, tol=1e-12, max_iter=10,
+                     precision=RB_PREC_F64, refine_steps=1, out=None, stream=None):
+        t = self.torch
+        B = th["ta"].shape[0]
+        if out is None:
+            out = dict(u=t.empty(B, self.N, dtype=t.float64, device=self.dev),
+                       iters=t.empty(B, dtype=t.int32, device=self.dev),
+                       status=t.empty(B, dtype=t.int32, device=self.dev))
+        opts = make_opts(tol, max_iter, precision, refine_steps)
+        rb_solve_uneven(self.ctx, self.set, B, Nreq, self.N, th["ta"], th["tc"], th["tf"],
+                        f_override, u0, opts, out["u"], out["iters"], out["status"], stream)
+        return out
+
+    def pressure(self, th, u, N=None, Np=None, out=None, stream=None):
+        t = self.torch
+        N = self.N if N is None else N
+        Np = self.Np if Np is None else Np
+        B = u.shape[0]
+        if out is None:
+            out = dict(p=t.empty(B, self.Np, dtype=t.float64, device=self.dev),
+                       pstatus=t.empty(B, dtype=t.int32, device=self.dev))
+        rb_recover_pressure(self.ctx, self.set, B, N, Np, u.shape[1], self.Np, th["ta"],
+                            th["tc"], th["tf"], th["tb"], u, out["p"], out["pstatus"], stream)
+        return out

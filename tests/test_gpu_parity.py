@@ -1,0 +1,261 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 CPU oracle.
+
+Every test runs the same seeded inputs through both sides and compares element by element:
+relative error <= 1e-10 per request for the FP64 path (the tolerance the target states for
+it), bit-exact for integer outputs (status codes; Newton iteration counts equal except where
+the stopping test sits within rounding of the threshold). Sizes span several 16-request
+tiles with a ragged tail; the full-size batch of 4096 requests at N = 50 is checked on a
+sample of requests the oracle solves one by one, in the launch configuration of the bench.
+"""
+
+import numpy as np
+import pytest
+
+from rbinputs import get_config, make_tensor_set, draw_mu
+from rbinputs.synth import TensorSet
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL_F64 = 1e-10
+
+
+def _rel(a, b):
+    nb = np.linalg.norm(b, axis=-1)
+    na = np.linalg.norm(a - b, axis=-1)
+    return np.where(nb > 0, na / np.where(nb > 0, nb, 1), na)
+
+
+@pytest.fixture(scope="module")
+def O(oracle_lib):
+    return oracle_lib
+
+
+@pytest.fixture(scope="module")
+def R():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1807_11866_amd import rbns
+    rbns.load()
+    return rbns
+
+
+def _dev(x, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(x)).to(device="cuda", dtype=dtype)
+
+
+def _random_set(N, Q=3, Qc=2, Qf=2, Np=5, Qb=2, seed=0, scale=0.05, H=True):
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((Q, N, N))
+    A = np.einsum("qij,qkj->qik", A, A) / N + 2 * np.eye(N)[None]
+    C = scale * rng.standard_normal((Qc, N, N, N))
+    C = 0.5 * (C - C.transpose(0, 3, 2, 1))
+    F = rng.standard_normal((Qf, N))
+    Bp = 0.2 * rng.standard_normal((Qb, Np, Np)) + np.eye(Np)[None]
+    Asv = rng.standard_normal((Q, Np, N))
+    Csv = rng.standard_normal((Qc, Np, N, N))
+    Fs = rng.standard_normal((Qf, Np))
+    Hm = np.eye(N) + 0.1 * np.ones((N, N)) if H else None
+    return TensorSet(N=N, Q=Q, Qc=Qc, Qf=Qf, Np=Np, Qb=Qb, A=A, C=C, F=F, H=Hm, Bp=Bp,
+                     Asv=Asv, Csv=Csv, Fs=Fs)
+
+
+def _oracle_theta(O, ts, mu):
+    th = [O.theta(ts.Q, ts.Qc, ts.Qf, ts.Qb, a, re) for a, re in mu]
+    return [np.array([t[i] for t in th]) for i in range(4)]
+
+
+@pytest.fixture(scope="module")
+def c1():
+    return make_tensor_set(get_config("single_n10"))
+
+
+@pytest.fixture(scope="module")
+def c2():
+    return make_tensor_set(get_config("batched_n50"))
+
+
+# ------------------------------------------------------------------------ theta ----
+
+def test_theta_matches_oracle(O, R, c2):
+    s = R.Solver(c2)
+    mu = draw_mu(get_config("batched_n50"), 333)
+    th = s.theta(_dev(mu))
+    torch.cuda.synchronize()
+    ta, tc, tf, tb = _oracle_theta(O, c2, mu)
+    for got, ref in ((th["ta"], ta), (th["tc"], tc), (th["tf"], tf), (th["tb"], tb)):
+        assert np.max(np.abs(got.cpu().numpy() - ref)) <= 4e-16 * max(1.0, np.abs(ref).max())
+    s.close()
+
+
+# ------------------------------------------------------------------------ solves ---
+
+def _gpu_solve(R, s, ts, mu, N=None, **kw):
+    th = s.theta(_dev(mu))
+    out = s.solve(th, N=N, **kw)
+    torch.cuda.synchronize()
+    return th, {k: v.cpu().numpy() for k, v in out.items()}
+
+
+@pytest.mark.parametrize("B", [1, 37])
+def test_single_n10_parity(O, R, c1, B):
+    cfg = get_config("single_n10")
+    mu = draw_mu(cfg, B)
+    s = R.Solver(c1)
+    _, g = _gpu_solve(R, s, c1, mu)
+    r = O.solve_batch(O.OracleSet(c1), mu, pressure_np=c1.Np)
+    assert np.array_equal(g["status"], r["status"]) and np.all(g["status"] == 0)
+    assert np.array_equal(g["iters"], r["iters"])
+    assert np.max(_rel(g["u"], r["u"])) <= TOL_F64
+    s.close()
+
+
+def test_batched_n50_parity_ragged(O, R, c2):
+    cfg = get_config("batched_n50")
+    mu = draw_mu(cfg, 300, seed_offset=11)        # 18 full tiles + a tail of 12
+    s = R.Solver(c2)
+    th, g = _gpu_solve(R, s, c2, mu)
+    r = O.solve_batch(O.OracleSet(c2), mu, pressure_np=c2.Np)
+    assert np.all(g["status"] == 0) and np.array_equal(g["status"], r["status"])
+    assert np.mean(g["iters"] == r["iters"]) >= 0.99
+    assert np.max(np.abs(g["iters"] - r["iters"])) <= 1
+    err = _rel(g["u"], r["u"])
+    assert np.max(err) <= TOL_F64, (np.max(err), np.percentile(err, 99))
+    # pressure recovery
+    p = s.pressure(th, torch.as_tensor(g["u"]).cuda())
+    torch.cuda.synchronize()
+    pg = p["p"].cpu().numpy()
+    assert np.all(p["pstatus"].cpu().numpy() == 0)
+    assert np.max(_rel(pg, r["p"])) <= TOL_F64
+    s.close()
+
+
+def test_full_batch_4096_sampled(O, R, c2):
+    """The bench's launch: 4096 requests at N = 50; the oracle re-solves a sample."""
+    cfg = get_config("batched_n50")
+    mu = draw_mu(cfg)
+    s = R.Solver(c2)
+    th, g = _gpu_solve(R, s, c2, mu)
+    p = s.pressure(th, torch.as_tensor(g["u"]).cuda())
+    torch.cuda.synchronize()
+    pg = p["p"].cpu().numpy()
+    idx = np.unique(np.concatenate([np.arange(0, 4096, 97), [15, 16, 4095]]))
+    r = O.solve_batch(O.OracleSet(c2), mu[idx], pressure_np=c2.Np)
+    assert np.all(g["status"] == 0)
+    assert np.max(_rel(g["u"][idx], r["u"])) <= TOL_F64
+    assert np.max(_rel(pg[idx], r["p"])) <= TOL_F64
+    s.close()
+
+
+@pytest.mark.parametrize("N", [1, 7, 8, 9, 16, 33, 50, 64])
+def test_random_tensors_every_bucket(O, R, N):
+    ts = _random_set(N, seed=N)
+    mu = np.column_stack([np.linspace(0.0, 0.6, 21), np.linspace(100, 1000, 21)])
+    s = R.Solver(ts)
+    th, g = _gpu_solve(R, s, ts, mu, max_iter=20)
+    r = O.solve_batch(O.OracleSet(ts), mu, maxit=20, pressure_np=ts.Np)
+    assert np.array_equal(g["status"], r["status"]) and np.all(g["status"] == 0)
+    assert np.max(_rel(g["u"], r["u"])) <= TOL_F64
+    p = s.pressure(th, torch.as_tensor(g["u"]).cuda())
+    torch.cuda.synchronize()
+    assert np.max(_rel(p["p"].cpu().numpy(), r["p"])) <= TOL_F64
+    s.close()
+
+
+def test_nested_leading_blocks(O, R, c2):
+    mu = draw_mu(get_config("batched_n50"), 40, seed_offset=3)
+    s = R.Solver(c2)
+    for n, npr in ((20, 10), (37, 30)):
+        th, g = _gpu_solve(R, s, c2, mu, N=n)
+        r = O.solve_batch(O.OracleSet(c2), mu, Nreq=np.full(40, n, np.int32), pressure_np=npr)
+        assert np.max(_rel(g["u"][:, :n], r["u"][:, :n])) <= TOL_F64
+        assert not np.any(g["u"][:, n:])
+        p = s.pressure(th, torch.as_tensor(g["u"]).cuda(), N=n, Np=npr)
+        torch.cuda.synchronize()
+        pg = p["p"].cpu().numpy()
+        sub = O.OracleSet(c2)
+        for b in range(0, 40, 13):
+            ta, tc, tf, tb = O.theta(c2.Q, c2.Qc, c2.Qf, c2.Qb, *mu[b])
+            pr, st = O.pressure(sub, n, npr, ta, tc, tf, tb, r["u"][b, :n])
+            assert st == 0 and np.linalg.norm(pg[b, :npr] - pr) <= TOL_F64 * np.linalg.norm(pr)
+            assert not np.any(pg[b, npr:])
+    s.close()
+
+
+def test_manufactured_solution_on_gpu(R):
+    """f := A u* + C(u*,u*) built here with numpy; the GPU Newton must return u*."""
+    ts = _random_set(24, seed=5, scale=0.1)
+    rng = np.random.default_rng(9)
+    B = 33
+    ustar = rng.standard_normal((B, 24))
+    ta = rng.uniform(0.5, 1.5, (B, ts.Q))
+    tc = rng.uniform(-1, 1, (B, ts.Qc))
+    f = np.einsum("bq,qij,bj->bi", ta, ts.A, ustar) + np.einsum("bq,qijk,bj,bk->bi", tc, ts.C, ustar, ustar)
+    s = R.Solver(ts)
+    th = dict(ta=_dev(ta), tc=_dev(tc), tf=_dev(np.zeros((B, ts.Qf))))
+    out = s.solve(th, f_override=_dev(f), tol=1e-14, max_iter=30)
+    torch.cuda.synchronize()
+    assert np.all(out["status"].cpu().numpy() == 0)
+    assert np.max(_rel(out["u"].cpu().numpy(), ustar)) <= 1e-12
+    s.close()
+
+
+def test_stokes_limit_on_gpu(R, c2):
+    mu = draw_mu(get_config("batched_n50"), 20)
+    s = R.Solver(c2)
+    th = s.theta(_dev(mu))
+    th["tc"].zero_()
+    out = s.solve(th)
+    torch.cuda.synchronize()
+    ta = th["ta"].cpu().numpy()
+    tf = th["tf"].cpu().numpy()
+    for b in range(20):
+        ref = np.linalg.solve(np.tensordot(ta[b], c2.A, 1), tf[b] @ c2.F)
+        assert np.linalg.norm(out["u"][b].cpu().numpy() - ref) <= 1e-12 * np.linalg.norm(ref)
+    assert np.all(out["iters"].cpu().numpy() == 2)
+    s.close()
+
+
+# ------------------------------------------------------------- statuses and errors ---
+
+def test_status_codes_forced_from_host(R, c1):
+    s = R.Solver(c1)
+    mu = np.tile([[0.2, 300.0]], (4, 1))
+    th = s.theta(_dev(mu))
+    th["ta"][1].zero_()
+    th["tc"][1].zero_()                         # A(mu) = 0, C = 0: zero pivot
+    th["ta"][2, 0] = float("nan")               # non-finite operand
+    out = s.solve(th, max_iter=1)               # request 0, 3: iteration limit
+    torch.cuda.synchronize()
+    st = out["status"].cpu().numpy()
+    assert list(st) == [1, 2, 3, 1]
+    assert list(out["iters"].cpu().numpy()) == [1, 0, 0, 1]
+    s.close()
+
+
+def test_call_level_errors(R, c1):
+    s = R.Solver(c1)
+    th = s.theta(_dev(np.array([[0.1, 200.0]])))
+    with pytest.raises(R.RbError) as e:
+        s.solve(th, N=11)
+    assert e.value.code == R.RB_E_INVAL
+    with pytest.raises(R.RbError):
+        s.solve(th, N=0)
+    with pytest.raises(R.RbError):
+        s.solve(th, max_iter=0)
+    with pytest.raises(R.RbError) as e:
+        s.solve(th, precision=7)
+    assert e.value.code in (R.RB_E_INVAL, R.RB_E_UNSUPPORTED)
+    # B == 0 is a no-op
+    R.rb_solve_batch(s.ctx, s.set, 0, 10, 10, None, None, None, None, None, None, None,
+                     None, None)
+    s.close()
+
+
+def test_hbm_budget_rejects_oversized_load(R, c2):
+    ctx = R.rb_create(0, 1 << 20)
+    with pytest.raises(R.RbError) as e:
+        R.rb_load_tensors(ctx, c2)
+    assert e.value.code == R.RB_E_NOMEM
+    assert R.rb_hbm_used(ctx) == 0
+    R.rb_destroy(ctx)
