@@ -115,11 +115,12 @@ __device__ __forceinline__ void wave_lds_order() {
 // afterwards, so every step runs unconditionally (no data-dependent control flow around the
 // register-resident rows). Rows are not moved between lanes: `pos` tracks each row's current
 // position so that the pivot choice (largest magnitude, ties to the smallest current row
-// index) is the one row-swapping elimination makes. The pivot row is broadcast through
-// `prow` (this wavefront's LDS row, >= NP + 1 entries); the right-hand side rides along as
-// an extra column. On return lane c < NP holds x_c in `x`. Returns 0, or RB_ST_SINGULAR (2)
+// index) is the one row-swapping elimination makes. The pivot row reaches the other lanes
+// either through `prow` (this wavefront's LDS row, >= NP + 1 entries; kLdsBcast) or lane by
+// lane through scalar registers (readlane); the right-hand side rides along as an extra
+// column. On return lane c < NP holds x_c in `x`. Returns 0, or RB_ST_SINGULAR (2)
 // if a pivot was zero (the values returned are then meaningless).
-template <int NP, typename T>
+template <int NP, bool kLdsBcast, typename T>
 __device__ __forceinline__ int lu_solve_rows(T (&a)[NP], T rhs, int lane, T* prow, T& x) {
   int pos = lane;
   bool singular = false;
@@ -144,41 +145,43 @@ __device__ __forceinline__ int lu_solve_rows(T (&a)[NP], T rhs, int lane, T* pro
     const int ppos = bcast(pos, pv);
     pos = (pos == k) ? ppos : pos;
     pos = (lane == pv) ? k : pos;
-#if defined(RB_LU_LDS_BCAST) && RB_LU_LDS_BCAST
-    if (lane == pv) {
-#pragma unroll
-      for (int j = k + 1; j < NP; ++j) prow[j] = a[j];
-      prow[NP] = rhs;
-    }
-    wave_lds_order();
     const T l = (pos > k) ? a[k] / piv : T(0);
+    if (kLdsBcast) {
+      if (lane == pv) {
 #pragma unroll
-    for (int j0 = k + 1; j0 < NP; j0 += 8) {
-      T pj[8];
+        for (int j = k + 1; j < NP; ++j) prow[j] = a[j];
+        prow[NP] = rhs;
+      }
+      wave_lds_order();
 #pragma unroll
-      for (int t = 0; t < 8; ++t)
-        if (j0 + t < NP) pj[t] = prow[j0 + t];
+      for (int j0 = k + 1; j0 < NP; j0 += 8) {
+        T pj[8];
 #pragma unroll
-      for (int t = 0; t < 8; ++t)
-        if (j0 + t < NP) a[j0 + t] = fma(-l, pj[t], a[j0 + t]);
-      __builtin_amdgcn_sched_barrier(0);
+        for (int t = 0; t < 8; ++t)
+          if (j0 + t < NP) pj[t] = prow[j0 + t];
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+          if (j0 + t < NP) a[j0 + t] = fma(-l, pj[t], a[j0 + t]);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      rhs = fma(-l, prow[NP], rhs);
+      wave_lds_order();
+    } else {
+      // Pivot-row entries go lane -> SGPR (readlane) and feed the FMA as its scalar operand,
+      // in chunks of 8 so the scalar registers in flight stay bounded.
+#pragma unroll
+      for (int j0 = k + 1; j0 < NP; j0 += 8) {
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+          if (j0 + t < NP) a[j0 + t] = fma(-l, bcast(a[j0 + t], pv), a[j0 + t]);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      rhs = fma(-l, bcast(rhs, pv), rhs);
     }
-    rhs = fma(-l, prow[NP], rhs);
-    wave_lds_order();
-#else
-    // Pivot-row entries go lane -> SGPR (readlane) and feed the FMA as its scalar operand,
-    // in chunks of 8 so the scalar registers in flight stay bounded.
-    const T l = (pos > k) ? a[k] / piv : T(0);
-#pragma unroll
-    for (int j0 = k + 1; j0 < NP; j0 += 8) {
-#pragma unroll
-      for (int t = 0; t < 8; ++t)
-        if (j0 + t < NP) a[j0 + t] = fma(-l, bcast(a[j0 + t], pv), a[j0 + t]);
-      __builtin_amdgcn_sched_barrier(0);
-    }
-    rhs = fma(-l, bcast(rhs, pv), rhs);
-#endif
   }
+  // Back substitution: the row that pivoted at step k (pos == k) holds U[k][k..] and the
+  // eliminated right-hand side; x_k = rhs / U[k][k], then every earlier pivot row drops its
+  // x_k term.
   x = T(0);
 #pragma unroll
   for (int k = NP - 1; k >= 0; --k) {

@@ -1,6 +1,6 @@
 // rb_kernels.hpp -- gfx950 kernels of the online reduced Navier-Stokes solver.
 //
-// Work decomposition (one workgroup = BT requests that share a basis size N):
+// Work decomposition (a workgroup tile = 32 requests that share a basis size N):
 //   * Jacobian + affine contraction on MFMA (paper Section 3.5 / 3.4): for the BT requests
 //       J[(i,j), b] = sum_k Op[(i,j), k] W[k, b],  Op = [ S_flat | A_flat ],
 //       S_q[i,j,l] = C_q[i,j,l] + C_q[i,l,j],  W = [ theta^c_q(b) u_l(b) ; theta^a_q(b) ],
@@ -21,7 +21,6 @@
 
 namespace rb {
 
-constexpr int kBT = 16;        // requests per workgroup = MFMA 16x16 output columns
 constexpr int kWaves = 4;      // wavefronts per workgroup
 constexpr int kThreads = kWave * kWaves;
 constexpr int kMaxQ = 12, kMaxQc = 4, kMaxQf = 2, kMaxQb = 2;
@@ -30,12 +29,16 @@ constexpr int kMaxQ = 12, kMaxQc = 4, kMaxQf = 2, kMaxQb = 2;
 // Packed operand layout for v_mfma_f64_16x16x4f64 (A operand: lane l holds row l%16,
 // k-column l/16 of a 16x4 tile): tile (rb, ks) = 64 consecutive doubles at
 // ((rb * nks + ks) * 64), element e <-> (row rb*16 + e%16, k = ks*4 + e/16).
-//
-// Solve operand rows: m = j*N + i (so J is written column-major per request); columns:
-// k < Qc*N -> S_q[i,j,l] with q = k / N, l = k % N; ks0*4 <= k < ks0*4 + Q -> A_q[i,j].
-__global__ void pack_solve_f64(const double* __restrict__ C, const double* __restrict__ A,
-                               int Nm, int N, int Q, int Qc, int nrb, int nks, int ksA,
-                               double* __restrict__ out) {
+// The k range of every row block is [ affine part: kA = ceil(Q/4) k-steps | tensor part:
+// KT k-steps = ceil(Qc*N/4) rounded up to even, zero padded ].
+// Solve operand rows: m = j*N + i (J is written column-major per request); columns:
+// k < Q -> A_q[i,j] (q = k); k = 4*kA + q*N + l -> S_q[i,j,l] = C_q[i,j,l] + C_q[i,l,j].
+// Pressure operand rows: m = j*Np + i; affine part A_sv, tensor part the unsymmetrised C_sv
+// (the epilogue contracts with u_j, giving A_sv u + C_sv(u,u)).
+template <bool kSolve>
+__global__ void pack_f64(const double* __restrict__ T3, const double* __restrict__ T2,
+                         int Nm, int Npm, int N, int R, int Q, int Qc, int kA, int nrb, int nks,
+                         double* __restrict__ out) {
   const int64_t total = (int64_t)nrb * nks * 64;
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.x * blockDim.x) {
@@ -44,39 +47,15 @@ __global__ void pack_solve_f64(const double* __restrict__ C, const double* __res
     const int rb = tile / nks, ks = tile % nks;
     const int m = rb * 16 + (e & 15), k = ks * 4 + (e >> 4);
     double v = 0.0;
-    if (m < N * N) {
-      const int j = m / N, i = m - j * N;
-      if (k < Qc * N) {
-        const int q = k / N, l = k - q * N;
-        v = C[(((int64_t)q * Nm + i) * Nm + j) * Nm + l] + C[(((int64_t)q * Nm + i) * Nm + l) * Nm + j];
-      } else if (k >= ksA * 4 && k < ksA * 4 + Q) {
-        v = A[((int64_t)(k - ksA * 4) * Nm + i) * Nm + j];
-      }
-    }
-    out[idx] = v;
-  }
-}
-
-// Pressure operand rows: m = j*Np + i; columns as for the solve operand but with the
-// unsymmetrised C_sv (the epilogue contracts with u_j, giving C_sv(u,u)) and A_sv.
-__global__ void pack_pressure_f64(const double* __restrict__ Csv, const double* __restrict__ Asv,
-                                  int Nm, int Npm, int N, int Np, int Q, int Qc, int nrb,
-                                  int nks, int ksA, double* __restrict__ out) {
-  const int64_t total = (int64_t)nrb * nks * 64;
-  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    const int e = idx & 63;
-    const int64_t tile = idx >> 6;
-    const int rb = tile / nks, ks = tile % nks;
-    const int m = rb * 16 + (e & 15), k = ks * 4 + (e >> 4);
-    double v = 0.0;
-    if (m < N * Np) {
-      const int j = m / Np, i = m - j * Np;
-      if (k < Qc * N) {
-        const int q = k / N, l = k - q * N;
-        v = Csv[(((int64_t)q * Npm + i) * Nm + j) * Nm + l];
-      } else if (k >= ksA * 4 && k < ksA * 4 + Q) {
-        v = Asv[((int64_t)(k - ksA * 4) * Npm + i) * Nm + j];
+    if (m < N * R) {
+      const int j = m / R, i = m - j * R;
+      const int Rm = kSolve ? Nm : Npm;        // stored row count of the test index
+      if (k < 4 * kA) {
+        if (k < Q) v = T2[((int64_t)k * Rm + i) * Nm + j];
+      } else if (k - 4 * kA < Qc * N) {
+        const int kk = k - 4 * kA, q = kk / N, l = kk - q * N;
+        v = T3[(((int64_t)q * Rm + i) * Nm + j) * Nm + l];
+        if (kSolve) v += T3[(((int64_t)q * Rm + i) * Nm + l) * Nm + j];
       }
     }
     out[idx] = v;
@@ -107,13 +86,14 @@ __global__ void theta_kernel(const double* __restrict__ mu, int B, int Q, int Qc
 }
 
 // ------------------------------------------------------------------ Newton (FP64) -----
-// Per-call device state of a batch solve (padded to whole 16-request tiles):
-//   U [Bp][NP] current iterates, Fv [Bp][NP] right-hand sides f(mu), Wv [Bp][NP] = J_c u,
+// Per-call device state of a batch solve (padded to whole 64-request tiles):
+//   U [Bp][NP] current iterates, Fv [Bp][NP] right-hand sides f(mu), Wv partial A(mu) u,
 //   J [Bp][mp] Jacobians (column-major, mp >= N*N), done/iters/status [Bp].
 struct NewtonState {
   double* U;
   double* Fv;
-  double* Wv;
+  double* Wv;              // [kSplit][Bp][NP] partial sums of A(mu) u
+  int64_t Bp;
   double* J;
   int* done;
   int* iters;
@@ -140,29 +120,9 @@ struct NewtonF64Args {
   NewtonState s;
 };
 
-// Build W[k][b] (k-major, kBT columns) from the current iterates: rows k < Qc*N hold
-// theta^c_q(b) u_l(b) (q = k/N, l = k%N), rows ksA*4 + q hold theta^a_q(b), the rest 0.
-__device__ __forceinline__ void build_w(double* __restrict__ Wl, const double* __restrict__ ul,
-                                        const double* __restrict__ tal,
-                                        const double* __restrict__ tcl, int NP, int N, int Q,
-                                        int Qc, int nks, int ksA) {
-  const int K = nks * 4;
-  for (int idx = threadIdx.x; idx < K * kBT; idx += blockDim.x) {
-    const int k = idx / kBT, b = idx - k * kBT;
-    double v = 0.0;
-    if (k < Qc * N) {
-      const int q = k / N, l = k - q * N;
-      v = tcl[b * kMaxQc + q] * ul[b * NP + l];
-    } else if (k >= ksA * 4 && k < ksA * 4 + Q) {
-      v = tal[b * kMaxQ + (k - ksA * 4)];
-    }
-    Wl[idx] = v;
-  }
-}
-
 // Start of a batch solve: iterates from u0 (or 0), f(mu) (or the override), flags.
 __global__ void newton_init_kernel(NewtonF64Args a) {
-  const int64_t Bp = (int64_t)(a.B + kBT - 1) / kBT * kBT;
+  const int64_t Bp = a.s.Bp;
   const int NP = a.s.NP, N = a.N;
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < Bp * NP;
        idx += (int64_t)gridDim.x * blockDim.x) {
@@ -187,72 +147,190 @@ __global__ void newton_init_kernel(NewtonF64Args a) {
   }
 }
 
-// Jacobian + residual contraction for 16 requests per workgroup (see file header).
-__global__ __launch_bounds__(kThreads) void jac_f64_kernel(NewtonF64Args a) {
+// ------------------------------------------------------------------ contraction ------
+// One MFMA-F64 contraction kernel serves both the Jacobian (+ residual) of a Newton step and
+// the pressure right-hand side. Workgroup g handles the 64-request tile g / kSplit and the
+// row split g % kSplit; with round-robin dispatch over the 8 XCDs every workgroup of one XCD
+// reads the same eighth of the packed operand, which therefore stays in that XCD's L2.
+// Wavefront w of the workgroup owns requests 16w..16w+15 of the tile and keeps its whole
+// slice of W (the B operand, kA + KT k-steps) in registers, so the main loop touches no LDS; the
+// four wavefronts walk the same row blocks in the same order and share each A tile (one
+// 512-byte line per k-step and row block) through L1. Row blocks go four at a time: per
+// k-step four A loads (issued kDepth k-steps ahead; the loop over the tensor k-steps is
+// unrolled at the compile-time length KT, so the pipeline is static) feed four
+// v_mfma_f64_16x16x4f64. The affine k-steps go first and are folded once per row group.
+//
+// Rows are m = j*R + i (R = N for the Jacobian, R = Np for the pressure). The epilogue
+// folds acc[m, b] * u_j(b) into per-row sums p_i(b) in LDS: for the Jacobian right after the
+// affine part of K (giving A(mu) u; with J u this yields F(u) = (J u + A u)/2 - f), for the
+// pressure after all of K (giving A_sv u + C_sv(u,u)). Each workgroup writes its split's
+// partial sums; the solve kernels add the kSplit partials.
+constexpr int kTile = 64;      // requests per workgroup tile (16 per wavefront)
+constexpr int kSplit = 8;      // row splits, one per XCD
+constexpr int kGroup = 4;      // row blocks per wavefront pass
+constexpr int kDepth = 4;      // k-steps of A operand in flight
+
+struct ContractArgs {
+  const double* op;        // packed operand [nrb][nks][64]
+  int nrb, nks, kA;        // row blocks, k-steps per row block (kA + KT), affine k-steps
+  int R, N, M;             // rows m = j*R + i, M = R*N
+  int Q, Qc, B;
+  int64_t Bp;              // padded request count (multiple of kTile)
+  const double* ta;        // [B][Q]
+  const double* tc;        // [B][Qc]
+  const double* U;         // iterates, row b at U + b*ldU (rows >= B are not read)
+  int ldU;
+  const int* done;         // Newton flags [Bp] or nullptr
+  double* J;               // Jacobian store [Bp][mp] or nullptr (pressure)
+  int64_t mp;
+  double* part;            // partial row sums [kSplit][Bp][ldp]
+  int ldp;
+};
+
+__host__ __device__ inline int64_t contract_lds_bytes(int N, int R) {
+  return 8 * ((int64_t)kTile * N + (int64_t)kTile * R + kTile * (kMaxQ + kMaxQc));
+}
+
+template <bool kJac, int KT>
+__global__ __launch_bounds__(kThreads) void contract_f64_kernel(ContractArgs a) {
   extern __shared__ double smem[];
-  const int K = a.nks * 4;
-  const int NP = a.s.NP;
-  double* Wl = smem;                       // [K][kBT]
-  double* ul = Wl + K * kBT;               // [kBT][NP]
-  double* wl = ul + kBT * NP;              // [kBT][NP]
-  double* tal = wl + kBT * NP;             // [kBT][kMaxQ]
-  double* tcl = tal + kBT * kMaxQ;         // [kBT][kMaxQc]
+  const int N = a.N, R = a.R;
+  const int kA = a.kA;                     // affine k-steps (1..3); tensor k-steps = KT
+  constexpr int kAmax = 3;
+  double* ul = smem;                       // [kTile][N]
+  double* pl = ul + kTile * N;             // [kTile][R]
+  double* tal = pl + kTile * R;            // [kTile][kMaxQ]
+  double* tcl = tal + kTile * kMaxQ;       // [kTile][kMaxQc]
 
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int b0 = blockIdx.x * kBT;
-  const int N = a.N, M = N * N;
-  if (__syncthreads_and(tid < kBT ? a.s.done[b0 + tid] : 1)) return;
+  const int split = blockIdx.x % kSplit;
+  const int b0 = (blockIdx.x / kSplit) * kTile;
+  if (kJac && __syncthreads_and(tid < kTile ? a.done[b0 + tid] : 1)) return;
 
-  for (int idx = tid; idx < kBT * NP; idx += kThreads) {
-    ul[idx] = a.s.U[(int64_t)b0 * NP + idx];
-    wl[idx] = 0.0;
+  for (int idx = tid; idx < kTile * N; idx += kThreads) {
+    const int b = idx / N, l = idx - b * N, bg = b0 + b;
+    ul[idx] = bg < a.B ? a.U[(int64_t)bg * a.ldU + l] : 0.0;
   }
-  for (int idx = tid; idx < kBT * kMaxQ; idx += kThreads) {
+  for (int idx = tid; idx < kTile * R; idx += kThreads) pl[idx] = 0.0;
+  for (int idx = tid; idx < kTile * kMaxQ; idx += kThreads) {
     const int b = idx / kMaxQ, q = idx - b * kMaxQ, bg = b0 + b;
     tal[idx] = (bg < a.B && q < a.Q) ? a.ta[(int64_t)bg * a.Q + q] : 0.0;
   }
-  for (int idx = tid; idx < kBT * kMaxQc; idx += kThreads) {
+  for (int idx = tid; idx < kTile * kMaxQc; idx += kThreads) {
     const int b = idx / kMaxQc, q = idx - b * kMaxQc, bg = b0 + b;
     tcl[idx] = (bg < a.B && q < a.Qc) ? a.tc[(int64_t)bg * a.Qc + q] : 0.0;
   }
   __syncthreads();
-  build_w(Wl, ul, tal, tcl, NP, N, a.Q, a.Qc, a.nks, a.nks_s);
-  __syncthreads();
 
-  const int bcol = lane & 15;
-  const double* wp = Wl + (lane >> 4) * kBT + bcol;
-  double* jcol = a.s.J + (int64_t)(b0 + bcol) * a.s.mp;
-  for (int rb = wv; rb < a.nrb; rb += kWaves) {
-    const double* opp = a.op + (int64_t)rb * a.nks * 64 + lane;
-    f64x4 acc = {0.0, 0.0, 0.0, 0.0};
-    int ks = 0;
-    for (; ks < a.nks_s; ++ks)
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(opp[ks * 64], wp[ks * 4 * kBT], acc, 0, 0, 0);
-    // epilogue: accumulate J_c[i,j] u_j into w_i. Accumulator layout of
-    // v_mfma_f64_16x16x4f64: lane l, element v holds row l/16 + 4v, column l%16.
-    const int m0 = rb * 16 + (lane >> 4);
+  // This lane's B-operand column: W[ks*4 + lane/16][b], b = 16*wv + lane%16. Affine part
+  // (rows k < 4*kA: theta^a_k), tensor part (row 4*kA + q*N + l: theta^c_q u_l).
+  const int bl = 16 * wv + (lane & 15);
+  const int k0 = lane >> 4;
+  double wA[kAmax], wT[KT];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int m = m0 + 4 * v;
-      if (m < M) {
-        const int j = m / N, i = m - j * N;
-        atomicAdd(&wl[bcol * NP + i], acc[v] * ul[bcol * NP + j]);
+  for (int ks = 0; ks < kAmax; ++ks) {
+    const int k = ks * 4 + k0;
+    wA[ks] = (k < kMaxQ) ? tal[bl * kMaxQ + k] : 0.0;
+  }
+  {
+    int l = k0, q = 0;
+    while (l >= N && q < kMaxQc) { l -= N; ++q; }
+#pragma unroll
+    for (int ks = 0; ks < KT; ++ks) {
+      wT[ks] = (q < a.Qc) ? tcl[bl * kMaxQc + q] * ul[bl * N + l] : 0.0;
+      l += 4;
+      while (l >= N && q < kMaxQc) { l -= N; ++q; }
+    }
+  }
+
+  const int rb_lo = (int)((int64_t)split * a.nrb / kSplit);
+  const int rb_hi = (int)((int64_t)(split + 1) * a.nrb / kSplit);
+  const int col = bl;                      // accumulator column (request) of this lane
+  const int nks = kA + KT;                 // k-steps per packed row block
+
+  for (int g0 = rb_lo; g0 < rb_hi; g0 += kGroup) {
+    const double* opg[kGroup];
+#pragma unroll
+    for (int r = 0; r < kGroup; ++r)
+      opg[r] = a.op + (int64_t)min(g0 + r, rb_hi - 1) * nks * 64 + lane;
+    double xa[kAmax][kGroup];
+#pragma unroll
+    for (int ks = 0; ks < kAmax; ++ks)
+#pragma unroll
+      for (int r = 0; r < kGroup; ++r) xa[ks][r] = opg[r][min(ks, kA - 1) * 64];
+    double x[KT][kGroup];
+#pragma unroll
+    for (int ks = 0; ks < kDepth && ks < KT; ++ks)
+#pragma unroll
+      for (int r = 0; r < kGroup; ++r) x[ks][r] = opg[r][(kA + ks) * 64];
+
+    f64x4 c[kGroup];
+#pragma unroll
+    for (int r = 0; r < kGroup; ++r) c[r] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int ks = 0; ks < kAmax; ++ks) {
+      if (ks < kA) {
+#pragma unroll
+        for (int r = 0; r < kGroup; ++r)
+          c[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[ks][r], wA[ks], c[r], 0, 0, 0);
       }
     }
-    for (; ks < a.nks; ++ks)
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(opp[ks * 64], wp[ks * 4 * kBT], acc, 0, 0, 0);
-    jcol[m0 + 0] = acc[0];
-    jcol[m0 + 4] = acc[1];
-    jcol[m0 + 8] = acc[2];
-    jcol[m0 + 12] = acc[3];
+
+    // Accumulator layout of v_mfma_f64_16x16x4f64: lane l, element v = row l/16 + 4v,
+    // column l%16 of the 16x16 tile. fold(): acc[m] * u_j into p_i for m = j*R + i.
+    auto fold = [&]() {
+      const int m0 = g0 * 16 + (lane >> 4);
+      const int j0 = m0 / R, i0 = m0 - j0 * R;
+#pragma unroll
+      for (int r = 0; r < kGroup; ++r) {
+        if (g0 + r < rb_hi) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            int i = i0 + 16 * r + 4 * v, j = j0;
+            while (i >= R) { i -= R; ++j; }
+            if (j < N) atomicAdd(&pl[col * R + i], c[r][v] * ul[col * N + j]);
+          }
+        }
+      }
+    };
+    if (kJac) fold();                      // affine part done: A(mu) u
+
+#pragma unroll
+    for (int ks = 0; ks < KT; ++ks) {
+      if (ks + kDepth < KT) {
+#pragma unroll
+        for (int r = 0; r < kGroup; ++r) x[ks + kDepth][r] = opg[r][(kA + ks + kDepth) * 64];
+      }
+#pragma unroll
+      for (int r = 0; r < kGroup; ++r)
+        c[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[ks][r], wT[ks], c[r], 0, 0, 0);
+    }
+
+    if (kJac) {
+#pragma unroll
+      for (int r = 0; r < kGroup; ++r) {
+        if (g0 + r < rb_hi) {
+          double* jp = a.J + (int64_t)(b0 + col) * a.mp + (g0 + r) * 16 + (lane >> 4);
+          jp[0] = c[r][0];
+          jp[4] = c[r][1];
+          jp[8] = c[r][2];
+          jp[12] = c[r][3];
+        }
+      }
+    } else {
+      fold();                              // A_sv u + C_sv(u,u)
+    }
   }
   __syncthreads();
-  for (int idx = tid; idx < kBT * NP; idx += kThreads) a.s.Wv[(int64_t)b0 * NP + idx] = wl[idx];
+  for (int idx = tid; idx < kTile * R; idx += kThreads) {
+    const int b = idx / R, i = idx - b * R;
+    a.part[((int64_t)split * a.Bp + b0 + b) * a.ldp + i] = pl[idx];
+  }
 }
 
-// One wavefront per request: residual F(u) = J u - w/2 - f, pivoted LU solve of
+// One wavefront per request: residual F(u) = (J u + A u)/2 - f, pivoted LU solve of
 // J delta = -F(u), update, and the stopping test ||delta||_H <= tol ||u||_H.
-template <int NP>
+template <int NP, bool kLdsBcast>
 __global__ __launch_bounds__(kThreads) void lu_f64_kernel(NewtonF64Args a, int it) {
   __shared__ double prow[kWaves][NP + 8];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -273,11 +351,16 @@ __global__ __launch_bounds__(kThreads) void lu_f64_kernel(NewtonF64Args a, int i
     bad |= !finite_val(r[c]);
   }
   double rhs = 0.0;
-  if (lane < N) rhs = -(ju - 0.5 * a.s.Wv[(int64_t)b * NP + lane] - a.s.Fv[(int64_t)b * NP + lane]);
+  if (lane < N) {
+    double w = 0.0;
+#pragma unroll
+    for (int sp = 0; sp < kSplit; ++sp) w += a.s.Wv[((int64_t)sp * a.s.Bp + b) * NP + lane];
+    rhs = -(0.5 * (ju + w) - a.s.Fv[(int64_t)b * NP + lane]);   // F(u) = (J u + A u)/2 - f
+  }
   bad |= !finite_val(rhs);
   int flag = __builtin_amdgcn_readfirstlane(__any(bad) ? 3 : 0);
   double dx = 0.0;
-  if (flag == 0) flag = lu_solve_rows<NP>(r, rhs, lane, &prow[wv][0], dx);
+  if (flag == 0) flag = lu_solve_rows<NP, kLdsBcast>(r, rhs, lane, &prow[wv][0], dx);
   if (flag == 0) {
     const double uo = lane < N ? ub[lane] : 0.0;
     const double un = uo + (lane < N ? dx : 0.0);
@@ -325,118 +408,58 @@ __global__ void newton_final_kernel(NewtonF64Args a) {
   }
 }
 
-__host__ __device__ inline int64_t jac_lds_bytes(int nks, int NP) {
-  return 8 * ((int64_t)nks * 4 * kBT + 2 * (int64_t)kBT * NP + kBT * (kMaxQ + kMaxQc));
-}
-
 // ------------------------------------------------------------------ pressure (FP64) ---
+// One wavefront per request: rhs = f_s(mu) - (A_sv u + C_sv(u,u)) (the contraction kernel's
+// partial sums), B(mu) = sum_q theta^b_q B_q, pivoted LU solve B(mu) p = rhs.
 struct PressureF64Args {
-  const double* op;        // packed pressure operand (rows (i,j), m = j*Np + i)
-  int nrb, nks_s, nks;
-  int N, Np, Nm, Npm, Q, Qc, Qf, Qb, B, ldu, ldp;
-  const double* ta;
-  const double* tc;
-  const double* tf;
-  const double* tb;
-  const double* u;         // [B][ldu]
+  int Np, Npm, Qf, Qb, B, ldp;
+  int64_t Bp;
+  const double* tf;        // [B][Qf]
+  const double* tb;        // [B][Qb]
   const double* BpT;       // [Qb][Npm][Npm] transposed: BpT[q][c][i] = B_q[i][c]
   const double* Fs;        // [Qf][Npm]
+  const double* part;      // [kSplit][Bp][NPP] partial sums of A_sv u + C_sv(u,u)
   double* p;               // [B][ldp]
   int* status;             // [B]
 };
 
-__host__ __device__ inline int64_t pressure_lds_bytes(int nks, int NPU, int NPP) {
-  return 8 * ((int64_t)nks * 4 * kBT + (int64_t)kBT * NPU + (int64_t)kBT * NPP +
-              kBT * (kMaxQ + kMaxQc) + kWaves * (NPP + 8));
-}
-
-template <int NPP>
-__global__ __launch_bounds__(kThreads) void pressure_f64_kernel(PressureF64Args a, int NPU) {
-  extern __shared__ double smem[];
-  const int K = a.nks * 4;
-  double* Wl = smem;                       // [K][kBT]
-  double* ul = Wl + K * kBT;               // [kBT][NPU]
-  double* rl = ul + kBT * NPU;             // [kBT][NPP] A_sv u + C_sv(u,u)
-  double* tal = rl + kBT * NPP;
-  double* tcl = tal + kBT * kMaxQ;
-  double* prow = tcl + kBT * kMaxQc;       // [kWaves][NPP + 8]
-
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int b0 = blockIdx.x * kBT;
-  const int N = a.N, Np = a.Np;
-  const int M = N * Np;
-  for (int idx = tid; idx < kBT * NPU; idx += kThreads) {
-    const int b = idx / NPU, i = idx - b * NPU, bg = b0 + b;
-    ul[idx] = (bg < a.B && i < N) ? a.u[(int64_t)bg * a.ldu + i] : 0.0;
-  }
-  for (int idx = tid; idx < kBT * NPP; idx += kThreads) rl[idx] = 0.0;
-  for (int idx = tid; idx < kBT * kMaxQ; idx += kThreads) {
-    const int b = idx / kMaxQ, q = idx - b * kMaxQ, bg = b0 + b;
-    tal[idx] = (bg < a.B && q < a.Q) ? a.ta[(int64_t)bg * a.Q + q] : 0.0;
-  }
-  for (int idx = tid; idx < kBT * kMaxQc; idx += kThreads) {
-    const int b = idx / kMaxQc, q = idx - b * kMaxQc, bg = b0 + b;
-    tcl[idx] = (bg < a.B && q < a.Qc) ? a.tc[(int64_t)bg * a.Qc + q] : 0.0;
-  }
-  __syncthreads();
-  build_w(Wl, ul, tal, tcl, NPU, N, a.Q, a.Qc, a.nks, a.nks_s);
-  __syncthreads();
-
-  const int bcol = lane & 15;
-  const double* wp = Wl + (lane >> 4) * kBT + bcol;
-  for (int rb = wv; rb < a.nrb; rb += kWaves) {
-    const double* opp = a.op + (int64_t)rb * a.nks * 64 + lane;
-    f64x4 acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
-    for (int ks = 0; ks < a.nks; ++ks)
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(opp[ks * 64], wp[ks * 4 * kBT], acc, 0, 0, 0);
-    const int m0 = rb * 16 + (lane >> 4);      // lane l, element v: row l/16 + 4v
+template <int NPP, bool kLdsBcast>
+__global__ __launch_bounds__(kThreads) void plu_f64_kernel(PressureF64Args a) {
+  __shared__ double prow[kWaves][NPP + 8];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int b = blockIdx.x * kWaves + wv;
+  if (b >= a.B) return;
+  const int Np = a.Np;
+  const int lc = lane < Np ? lane : Np - 1;
+  double tbv[kMaxQb];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int m = m0 + 4 * v;
-      if (m < M) {
-        const int j = m / Np, i = m - j * Np;
-        atomicAdd(&rl[bcol * NPP + i], acc[v] * ul[bcol * NPU + j]);
-      }
-    }
+  for (int q = 0; q < kMaxQb; ++q) tbv[q] = q < a.Qb ? a.tb[(int64_t)b * a.Qb + q] : 0.0;
+  double r[NPP];
+  bool bad = false;
+#pragma unroll
+  for (int c = 0; c < NPP; ++c) {
+    const int cc = c < Np ? c : Np - 1;
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < kMaxQb; ++q)
+      if (q < a.Qb) s = fma(tbv[q], a.BpT[((int64_t)q * a.Npm + cc) * a.Npm + lc], s);
+    r[c] = (c < Np && lane < Np) ? s : (c == lane ? 1.0 : 0.0);
+    bad |= !finite_val(r[c]);
   }
-  __syncthreads();
-
-  for (int b = wv; b < kBT; b += kWaves) {
-    const int bg = b0 + b;
-    if (bg >= a.B) continue;
-    double r[NPP];
-    double tbv[kMaxQb];
+  double rhs = 0.0;
+  if (lane < Np) {
+    for (int q = 0; q < a.Qf; ++q) rhs = fma(a.tf[(int64_t)b * a.Qf + q], a.Fs[(int64_t)q * a.Npm + lane], rhs);
 #pragma unroll
-    for (int q = 0; q < kMaxQb; ++q) tbv[q] = q < a.Qb ? a.tb[(int64_t)bg * a.Qb + q] : 0.0;
-#pragma unroll
-    for (int c = 0; c < NPP; ++c) {
-      double s = 0.0;
-      if (c < Np && lane < Np) {
-        for (int q = 0; q < a.Qb; ++q)
-          s = fma(tbv[q], a.BpT[((int64_t)q * a.Npm + c) * a.Npm + lane], s);
-      } else if (c == lane) {
-        s = 1.0;
-      }
-      r[c] = s;
-    }
-    double rhs = 0.0;
-    if (lane < Np) {
-      for (int q = 0; q < a.Qf; ++q)
-        rhs = fma(a.tf[(int64_t)bg * a.Qf + q], a.Fs[(int64_t)q * a.Npm + lane], rhs);
-      rhs -= rl[b * NPP + lane];
-    }
-    bool bad = !finite_val(rhs);
-#pragma unroll
-    for (int c = 0; c < NPP; ++c) bad |= !finite_val(r[c]);
-    int flag = __builtin_amdgcn_readfirstlane(__any(bad) ? 3 : 0);
-    double x = 0.0;
-    if (flag == 0) flag = lu_solve_rows<NPP>(r, rhs, lane, prow + wv * (NPP + 8), x);
-    if (flag == 0 && !finite_val(wave_sum(x))) flag = 3;
-    for (int i = lane; i < a.ldp; i += kWave)
-      a.p[(int64_t)bg * a.ldp + i] = (flag == 0 && i < Np) ? (i == lane ? x : 0.0) : 0.0;
-    if (lane == 0) a.status[bg] = flag;
+    for (int sp = 0; sp < kSplit; ++sp) rhs -= a.part[((int64_t)sp * a.Bp + b) * NPP + lane];
   }
+  bad |= !finite_val(rhs);
+  int flag = __builtin_amdgcn_readfirstlane(__any(bad) ? 3 : 0);
+  double x = 0.0;
+  if (flag == 0) flag = lu_solve_rows<NPP, kLdsBcast>(r, rhs, lane, &prow[wv][0], x);
+  if (flag == 0 && !finite_val(wave_sum(lane < Np ? x : 0.0))) flag = 3;
+  for (int i = lane; i < a.ldp; i += kWave)
+    a.p[(int64_t)b * a.ldp + i] = (flag == 0 && i < Np) ? x : 0.0;
+  if (lane == 0) a.status[b] = flag;
 }
 
 }  // namespace rb

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdarg>
+#include <cstdlib>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -74,6 +75,7 @@ struct rb_ctx {
   std::map<void*, Workspace> ws;
   std::mutex mu;
   bool timing = false;
+  bool lu_lds = false;                  // pivot-row broadcast through LDS instead of readlane
   std::vector<TimedLaunch> timed;       // recorded, not yet read
   std::vector<hipEvent_t> event_pool;
 };
@@ -127,23 +129,39 @@ int launch_grid(int64_t total) {
 }
 
 // Solve operand for basis size N (built once on the device, then cached).
+// k-steps of a packed row block: affine part ceil(Q/4), tensor part ceil(Qc*N/4) rounded up
+// to even (the contraction kernel is instantiated per even tensor length).
+int affine_ksteps(int Q) { return (Q + 3) / 4; }
+int tensor_ksteps(int Qc, int N) { return (int)ceil_to(ceil_to((int64_t)Qc * N, 4) / 4, 2); }
+int total_ksteps(int Q, int Qc, int N) { return affine_ksteps(Q) + tensor_ksteps(Qc, N); }
+
+int make_pack(rb_ctx* c, Set* s, int N, int R, bool solve, Pack* p) {
+  p->nrb = (int)(ceil_to((int64_t)N * R, 16) / 16);
+  p->nks_s = affine_ksteps(s->Q);
+  p->nks = total_ksteps(s->Q, s->Qc, N);
+  const int64_t total = (int64_t)p->nrb * p->nks * 64;
+  int rc = dev_alloc(c, p->buf, total * sizeof(double));
+  if (rc) return rc;
+  if (solve)
+    hipLaunchKernelGGL(rb::pack_f64<true>, dim3(launch_grid(total)), dim3(256), 0, 0,
+                       (const double*)s->C.p, (const double*)s->A.p, s->N, s->N, N, N, s->Q,
+                       s->Qc, p->nks_s, p->nrb, p->nks, (double*)p->buf.p);
+  else
+    hipLaunchKernelGGL(rb::pack_f64<false>, dim3(launch_grid(total)), dim3(256), 0, 0,
+                       (const double*)s->Csv.p, (const double*)s->Asv.p, s->N, s->Np, N, R,
+                       s->Q, s->Qc, p->nks_s, p->nrb, p->nks, (double*)p->buf.p);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipDeviceSynchronize());
+  return RB_OK;
+}
+
+// Solve operand for basis size N (built once on the device, then cached).
 int solve_pack_f64(rb_ctx* c, Set* s, int N, Pack** out) {
   auto it = s->solve_f64.find(N);
   if (it != s->solve_f64.end()) { *out = &it->second; return RB_OK; }
   Pack p;
-  p.nrb = (int)(ceil_to((int64_t)N * N, 16) / 16);
-  p.nks_s = (int)(ceil_to((int64_t)s->Qc * N, 4) / 4);
-  p.nks = p.nks_s + (int)(ceil_to(s->Q, 4) / 4);
-  const int64_t total = (int64_t)p.nrb * p.nks * 64;
-  int rc = dev_alloc(c, p.buf, total * sizeof(double));
-  if (rc) return rc;
-  hipLaunchKernelGGL(rb::pack_solve_f64, dim3(launch_grid(total)), dim3(256), 0, 0,
-                     (const double*)s->C.p, (const double*)s->A.p, s->N, N, s->Q, s->Qc,
-                     p.nrb, p.nks, p.nks_s, (double*)p.buf.p);
-  HIP_TRY(hipGetLastError());
-  HIP_TRY(hipDeviceSynchronize());
-  auto ins = s->solve_f64.emplace(N, p);
-  *out = &ins.first->second;
+  if (int rc = make_pack(c, s, N, N, true, &p)) return rc;
+  *out = &s->solve_f64.emplace(N, p).first->second;
   return RB_OK;
 }
 
@@ -152,20 +170,35 @@ int press_pack_f64(rb_ctx* c, Set* s, int N, int Np, Pack** out) {
   auto it = s->press_f64.find(key);
   if (it != s->press_f64.end()) { *out = &it->second; return RB_OK; }
   Pack p;
-  p.nrb = (int)(ceil_to((int64_t)N * Np, 16) / 16);
-  p.nks_s = (int)(ceil_to((int64_t)s->Qc * N, 4) / 4);
-  p.nks = p.nks_s + (int)(ceil_to(s->Q, 4) / 4);
-  const int64_t total = (int64_t)p.nrb * p.nks * 64;
-  int rc = dev_alloc(c, p.buf, total * sizeof(double));
-  if (rc) return rc;
-  hipLaunchKernelGGL(rb::pack_pressure_f64, dim3(launch_grid(total)), dim3(256), 0, 0,
-                     (const double*)s->Csv.p, (const double*)s->Asv.p, s->N, s->Np, N, Np,
-                     s->Q, s->Qc, p.nrb, p.nks, p.nks_s, (double*)p.buf.p);
-  HIP_TRY(hipGetLastError());
-  HIP_TRY(hipDeviceSynchronize());
-  auto ins = s->press_f64.emplace(key, p);
-  *out = &ins.first->second;
+  if (int rc = make_pack(c, s, N, Np, false, &p)) return rc;
+  *out = &s->press_f64.emplace(key, p).first->second;
   return RB_OK;
+}
+
+// Launch the contraction kernel instantiated for the operand's tensor k-step count.
+template <bool kJac, int KT>
+int launch_contract_kt(const rb::ContractArgs& g, hipStream_t st) {
+  const size_t lds = (size_t)rb::contract_lds_bytes(g.N, g.R);
+  if (lds > 64 * 1024)
+    HIP_TRY(hipFuncSetAttribute((const void*)rb::contract_f64_kernel<kJac, KT>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  const int grid = (int)(g.Bp / rb::kTile) * rb::kSplit;
+  hipLaunchKernelGGL((rb::contract_f64_kernel<kJac, KT>), dim3(grid), dim3(rb::kThreads), lds,
+                     st, g);
+  return RB_OK;
+}
+
+template <bool kJac>
+int launch_contract(const rb::ContractArgs& g, hipStream_t st) {
+  switch (g.nks - g.kA) {
+#define RB_KT(n) case n: return launch_contract_kt<kJac, n>(g, st);
+    RB_KT(2) RB_KT(4) RB_KT(6) RB_KT(8) RB_KT(10) RB_KT(12) RB_KT(14) RB_KT(16) RB_KT(18)
+    RB_KT(20) RB_KT(22) RB_KT(24) RB_KT(26) RB_KT(28) RB_KT(30) RB_KT(32) RB_KT(34) RB_KT(36)
+    RB_KT(38) RB_KT(40) RB_KT(42) RB_KT(44) RB_KT(46) RB_KT(48) RB_KT(50) RB_KT(52) RB_KT(54)
+    RB_KT(56) RB_KT(58) RB_KT(60) RB_KT(62) RB_KT(64)
+#undef RB_KT
+  }
+  return fail(RB_E_UNSUPPORTED, "contraction with %d tensor k-steps not built", g.nks - g.kA);
 }
 
 int workspace(rb_ctx* c, void* stream, size_t bytes, Workspace** out) {
@@ -185,7 +218,8 @@ int workspace(rb_ctx* c, void* stream, size_t bytes, Workspace** out) {
 
 // Carve the Newton state for Bp (padded) requests out of one workspace allocation.
 size_t newton_state_bytes(int64_t Bp, int NP, int64_t mp) {
-  return (size_t)(Bp * mp + 3 * Bp * NP) * sizeof(double) + (size_t)3 * Bp * sizeof(int) + 256;
+  return (size_t)(Bp * mp + (2 + rb::kSplit) * Bp * NP) * sizeof(double) +
+         (size_t)3 * Bp * sizeof(int) + 256;
 }
 
 rb::NewtonState carve_state(void* base, int64_t Bp, int NP, int64_t mp) {
@@ -198,17 +232,18 @@ rb::NewtonState carve_state(void* base, int64_t Bp, int NP, int64_t mp) {
   s.Fv = d;
   d += Bp * NP;
   s.Wv = d;
-  d += Bp * NP;
+  d += rb::kSplit * Bp * NP;
   int* ip = (int*)d;
   s.done = ip;
   s.iters = ip + Bp;
   s.status = ip + 2 * Bp;
   s.mp = mp;
   s.NP = NP;
+  s.Bp = Bp;
   return s;
 }
 
-int np_bucket(int n) { return (int)ceil_to(n, 8); }
+int np_bucket(int n) { return (int)ceil_to(n, 4); }
 
 enum { FAM_JACOBIAN = 0, FAM_LU = 1, FAM_PRESSURE = 2, FAM_COUNT = 3 };
 const char* const kFamilies[FAM_COUNT] = {"jacobian", "lu", "pressure"};
@@ -246,22 +281,33 @@ struct LaunchTimer {
 };
 
 template <int NP>
-int launch_lu(const rb::NewtonF64Args& a, int it, hipStream_t st) {
-  hipLaunchKernelGGL(rb::lu_f64_kernel<NP>, dim3((a.B + rb::kWaves - 1) / rb::kWaves),
-                     dim3(rb::kThreads), 0, st, a, it);
+int launch_lu(const rb::NewtonF64Args& a, int it, bool lds, hipStream_t st) {
+  const dim3 grid((a.B + rb::kWaves - 1) / rb::kWaves);
+  if (lds)
+    hipLaunchKernelGGL((rb::lu_f64_kernel<NP, true>), grid, dim3(rb::kThreads), 0, st, a, it);
+  else
+    hipLaunchKernelGGL((rb::lu_f64_kernel<NP, false>), grid, dim3(rb::kThreads), 0, st, a, it);
   return RB_OK;
 }
 
-int dispatch_lu(int NP, const rb::NewtonF64Args& a, int it, hipStream_t st) {
+int dispatch_lu(int NP, const rb::NewtonF64Args& a, int it, bool lds, hipStream_t st) {
   switch (NP) {
-    case 8: return launch_lu<8>(a, it, st);
-    case 16: return launch_lu<16>(a, it, st);
-    case 24: return launch_lu<24>(a, it, st);
-    case 32: return launch_lu<32>(a, it, st);
-    case 40: return launch_lu<40>(a, it, st);
-    case 48: return launch_lu<48>(a, it, st);
-    case 56: return launch_lu<56>(a, it, st);
-    case 64: return launch_lu<64>(a, it, st);
+    case 4: return launch_lu<4>(a, it, lds, st);
+    case 8: return launch_lu<8>(a, it, lds, st);
+    case 12: return launch_lu<12>(a, it, lds, st);
+    case 16: return launch_lu<16>(a, it, lds, st);
+    case 20: return launch_lu<20>(a, it, lds, st);
+    case 24: return launch_lu<24>(a, it, lds, st);
+    case 28: return launch_lu<28>(a, it, lds, st);
+    case 32: return launch_lu<32>(a, it, lds, st);
+    case 36: return launch_lu<36>(a, it, lds, st);
+    case 40: return launch_lu<40>(a, it, lds, st);
+    case 44: return launch_lu<44>(a, it, lds, st);
+    case 48: return launch_lu<48>(a, it, lds, st);
+    case 52: return launch_lu<52>(a, it, lds, st);
+    case 56: return launch_lu<56>(a, it, lds, st);
+    case 60: return launch_lu<60>(a, it, lds, st);
+    case 64: return launch_lu<64>(a, it, lds, st);
   }
   return fail(RB_E_UNSUPPORTED, "basis size bucket %d not built", NP);
 }
@@ -270,20 +316,25 @@ int dispatch_lu(int NP, const rb::NewtonF64Args& a, int it, hipStream_t st) {
 // final copy-out. Converged requests are skipped by both kernels through the done flags.
 int enqueue_newton(rb_ctx* c, const rb::NewtonF64Args& a, hipStream_t st) {
   const int NP = a.s.NP;
-  const int64_t Bp = (int64_t)(a.B + rb::kBT - 1) / rb::kBT * rb::kBT;
-  const size_t lds = (size_t)rb::jac_lds_bytes(a.nks, NP);
-  if (lds > 64 * 1024)
-    HIP_TRY(hipFuncSetAttribute((const void*)rb::jac_f64_kernel,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  const int64_t Bp = a.s.Bp;
+  rb::ContractArgs g;
+  g.op = a.op;
+  g.nrb = a.nrb; g.nks = a.nks; g.kA = a.nks_s;
+  g.R = a.N; g.N = a.N; g.M = a.N * a.N;
+  g.Q = a.Q; g.Qc = a.Qc; g.B = a.B; g.Bp = Bp;
+  g.ta = a.ta; g.tc = a.tc;
+  g.U = a.s.U; g.ldU = NP;
+  g.done = a.s.done;
+  g.J = a.s.J; g.mp = a.s.mp;
+  g.part = a.s.Wv; g.ldp = NP;
   hipLaunchKernelGGL(rb::newton_init_kernel, dim3(launch_grid(Bp * NP)), dim3(256), 0, st, a);
   for (int it = 0; it < a.maxit; ++it) {
     {
       LaunchTimer t(c, FAM_JACOBIAN, st);
-      hipLaunchKernelGGL(rb::jac_f64_kernel, dim3(Bp / rb::kBT), dim3(rb::kThreads), lds, st,
-                         a);
+      if (int rc = launch_contract<true>(g, st)) return rc;
     }
     LaunchTimer t(c, FAM_LU, st);
-    if (int rc = dispatch_lu(NP, a, it, st)) return rc;
+    if (int rc = dispatch_lu(NP, a, it, c->lu_lds, st)) return rc;
   }
   hipLaunchKernelGGL(rb::newton_final_kernel, dim3(launch_grid((int64_t)a.B * a.ldu)),
                      dim3(256), 0, st, a);
@@ -292,28 +343,33 @@ int enqueue_newton(rb_ctx* c, const rb::NewtonF64Args& a, hipStream_t st) {
 }
 
 template <int NPP>
-int launch_pressure(const rb::PressureF64Args& a, int NPU, hipStream_t st) {
-  const size_t lds = (size_t)rb::pressure_lds_bytes(a.nks, NPU, NPP);
-  if (lds > 64 * 1024)
-    HIP_TRY(hipFuncSetAttribute((const void*)rb::pressure_f64_kernel<NPP>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  const int grid = (a.B + rb::kBT - 1) / rb::kBT;
-  hipLaunchKernelGGL(rb::pressure_f64_kernel<NPP>, dim3(grid), dim3(rb::kThreads), lds, st,
-                     a, NPU);
-  HIP_TRY(hipGetLastError());
+int launch_plu(const rb::PressureF64Args& a, bool lds, hipStream_t st) {
+  const dim3 grid((a.B + rb::kWaves - 1) / rb::kWaves);
+  if (lds)
+    hipLaunchKernelGGL((rb::plu_f64_kernel<NPP, true>), grid, dim3(rb::kThreads), 0, st, a);
+  else
+    hipLaunchKernelGGL((rb::plu_f64_kernel<NPP, false>), grid, dim3(rb::kThreads), 0, st, a);
   return RB_OK;
 }
 
-int dispatch_pressure(int NPP, const rb::PressureF64Args& a, int NPU, hipStream_t st) {
+int dispatch_plu(int NPP, const rb::PressureF64Args& a, bool lds, hipStream_t st) {
   switch (NPP) {
-    case 8: return launch_pressure<8>(a, NPU, st);
-    case 16: return launch_pressure<16>(a, NPU, st);
-    case 24: return launch_pressure<24>(a, NPU, st);
-    case 32: return launch_pressure<32>(a, NPU, st);
-    case 40: return launch_pressure<40>(a, NPU, st);
-    case 48: return launch_pressure<48>(a, NPU, st);
-    case 56: return launch_pressure<56>(a, NPU, st);
-    case 64: return launch_pressure<64>(a, NPU, st);
+    case 4: return launch_plu<4>(a, lds, st);
+    case 8: return launch_plu<8>(a, lds, st);
+    case 12: return launch_plu<12>(a, lds, st);
+    case 16: return launch_plu<16>(a, lds, st);
+    case 20: return launch_plu<20>(a, lds, st);
+    case 24: return launch_plu<24>(a, lds, st);
+    case 28: return launch_plu<28>(a, lds, st);
+    case 32: return launch_plu<32>(a, lds, st);
+    case 36: return launch_plu<36>(a, lds, st);
+    case 40: return launch_plu<40>(a, lds, st);
+    case 44: return launch_plu<44>(a, lds, st);
+    case 48: return launch_plu<48>(a, lds, st);
+    case 52: return launch_plu<52>(a, lds, st);
+    case 56: return launch_plu<56>(a, lds, st);
+    case 60: return launch_plu<60>(a, lds, st);
+    case 64: return launch_plu<64>(a, lds, st);
   }
   return fail(RB_E_UNSUPPORTED, "pressure size bucket %d not built", NPP);
 }
@@ -335,6 +391,7 @@ int rb_create(int device, size_t hbm_budget_bytes, rb_ctx** out) {
   rb_ctx* c = new rb_ctx;
   c->device = device;
   c->budget = hbm_budget_bytes;
+  if (const char* v = getenv("RB_LU_BCAST")) c->lu_lds = (strcmp(v, "lds") == 0);
   *out = c;
   g_err.clear();
   return RB_OK;
@@ -457,7 +514,7 @@ int rb_solve_batch(rb_ctx* c, int set, int B, int N, int ldu, const double* ta,
   if (int rc = solve_pack_f64(c, s, N, &pk)) return rc;
   const int64_t mp = ceil_to((int64_t)N * N, 16);
   const int NP = np_bucket(N);
-  const int64_t Bp = ceil_to(B, rb::kBT);
+  const int64_t Bp = ceil_to(B, rb::kTile);
   Workspace* w;
   if (int rc = workspace(c, stream, newton_state_bytes(Bp, NP, mp), &w)) return rc;
   rb::NewtonF64Args a;
@@ -500,17 +557,33 @@ int rb_recover_pressure(rb_ctx* c, int set, int B, int N, int Np, int ldu, int l
   if (int rc = use_device(c)) return rc;
   Pack* pk;
   if (int rc = press_pack_f64(c, s, N, Np, &pk)) return rc;
+  const int NPP = np_bucket(Np);
+  const int64_t Bp = ceil_to(B, rb::kTile);
+  Workspace* w;
+  if (int rc = workspace(c, stream, (size_t)rb::kSplit * Bp * NPP * sizeof(double), &w)) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  rb::ContractArgs g;
+  g.op = (const double*)pk->buf.p;
+  g.nrb = pk->nrb; g.nks = pk->nks; g.kA = pk->nks_s;
+  g.R = Np; g.N = N; g.M = Np * N;
+  g.Q = s->Q; g.Qc = s->Qc; g.B = B; g.Bp = Bp;
+  g.ta = ta; g.tc = tc;
+  g.U = u; g.ldU = ldu;
+  g.done = nullptr;
+  g.J = nullptr; g.mp = 0;
+  g.part = (double*)w->buf.p; g.ldp = NPP;
   rb::PressureF64Args a;
-  a.op = (const double*)pk->buf.p;
-  a.nrb = pk->nrb; a.nks_s = pk->nks_s; a.nks = pk->nks;
-  a.N = N; a.Np = Np; a.Nm = s->N; a.Npm = s->Np; a.Q = s->Q; a.Qc = s->Qc; a.Qf = s->Qf;
-  a.Qb = s->Qb; a.B = B; a.ldu = ldu; a.ldp = ldp;
-  a.ta = ta; a.tc = tc; a.tf = tf; a.tb = tb; a.u = u;
+  a.Np = Np; a.Npm = s->Np; a.Qf = s->Qf; a.Qb = s->Qb; a.B = B; a.ldp = ldp; a.Bp = Bp;
+  a.tf = tf; a.tb = tb;
   a.BpT = (const double*)s->BpT.p;
   a.Fs = (const double*)s->Fs.p;
+  a.part = g.part;
   a.p = p; a.status = status;
-  LaunchTimer t(c, FAM_PRESSURE, (hipStream_t)stream);
-  return dispatch_pressure(np_bucket(Np), a, N, (hipStream_t)stream);
+  LaunchTimer t(c, FAM_PRESSURE, st);
+  if (int rc = launch_contract<false>(g, st)) return rc;
+  if (int rc = dispatch_plu(NPP, a, c->lu_lds, st)) return rc;
+  HIP_TRY(hipGetLastError());
+  return RB_OK;
 }
 
 int rb_timing_enable(rb_ctx* c, int enable) {
