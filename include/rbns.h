@@ -50,7 +50,9 @@ extern "C" {
 
 /* arithmetic of the Newton iteration */
 #define RB_PREC_F64      0    /* FP64 tensors, FP64 MFMA contraction, FP64 LU                */
-#define RB_PREC_F32      1    /* FP32 contraction + FP32 LU, then FP64 residual refinement   */
+#define RB_PREC_F32      1    /* FP32 tensors + FP32 MFMA contraction, FP32 LU, FP64 iterates,
+                                 then FP64-residual refinement steps                          */
+#define RB_PREC_BF16     2    /* as RB_PREC_F32 with BF16 tensors on BF16 MFMA (FP32 accum.) */
 
 typedef struct rb_ctx rb_ctx;
 
@@ -79,10 +81,14 @@ typedef struct {
 
 typedef struct {
     double tol;          /* stop when ||delta|| <= tol * ||u|| (norm given by H)           */
-    int max_iter;        /* Newton iteration limit (>= 1)                                    */
+    int max_iter;        /* Newton iteration limit (>= 1); for the mixed precisions, the
+                            limit of the low-precision phase                                 */
     int precision;       /* RB_PREC_*                                                        */
-    int refine_steps;    /* RB_PREC_F32 only: FP64-residual refinement steps after the FP32
-                            iteration has stagnated (>= 1)                                   */
+    int refine_steps;    /* mixed precisions only (0..100): at most this many refinement
+                            steps after the low-precision phase; each evaluates the residual
+                            F(u) from the FP64 tensors, solves with the low-precision
+                            Jacobian of the last low-precision step and adds the correction
+                            to the FP64 iterate                                              */
 } rb_solve_opts;
 
 /* Size limits of this build (the LU keeps one system row per lane of a 64-wide wavefront). */
@@ -139,6 +145,12 @@ int rb_theta(rb_ctx *ctx, int set, int B, const double *mu, double *theta_a, dou
  * Device outputs: u [B][ldu] (entries >= N are set to 0), iters [B] (Newton updates applied),
  * status [B] (RB_ST_*). ldu >= N is the row stride of u0 / f_override / u.
  * opts == NULL selects tol 1e-12, max_iter 10, RB_PREC_F64.
+ * Mixed precisions (RB_PREC_F32 / RB_PREC_BF16): the low-precision phase stops a request when
+ * its update is below tol or has stagnated (update <= 1e-3 ||u|| for FP32, 5e-2 ||u|| for BF16,
+ * and no longer halving), or at max_iter. Then every request without a failure status takes
+ * up to refine_steps refinement steps (FP64 residual, the Jacobian of its last low-precision
+ * step) until an update is below tol (status RB_ST_CONVERGED, else RB_ST_MAXIT). iters
+ * counts both kinds of updates.
  * Errors: RB_E_INVAL (NULL, B < 0, N or ldu out of range, bad opts), RB_E_NOMEM,
  * RB_E_UNSUPPORTED, RB_E_DEVICE. B == 0 is a no-op.
  */
@@ -183,6 +195,7 @@ int rb_recover_pressure(rb_ctx *ctx, int set, int B, int N, int Np, int ldu, int
  * Errors: RB_E_INVAL (unknown family), RB_E_DEVICE.
  */
 int rb_timing_enable(rb_ctx *ctx, int enable);
+/* (family "residual": the FP64 residual contraction of the mixed-precision refinement) */
 int rb_timing_read(rb_ctx *ctx, const char *family, double *total_ms, int *launches);
 
 #ifdef __cplusplus

@@ -63,7 +63,7 @@ __global__ void pack_f64(const double* __restrict__ T3, const double* __restrict
 }
 
 // ------------------------------------------------------------------ theta(mu) ---------
-__global__ void theta_kernel(const double* __restrict__ mu, int B, int Q, int Qc, int Qf,
+static __global__ void theta_kernel(const double* __restrict__ mu, int B, int Q, int Qc, int Qf,
                              int Qb, double* __restrict__ ta, double* __restrict__ tc,
                              double* __restrict__ tf, double* __restrict__ tb) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
@@ -98,6 +98,7 @@ struct NewtonState {
   int* done;
   int* iters;
   int* status;
+  double* dprev;           // previous update norm (stagnation test of the low-precision phase)
   int64_t mp;
   int NP;
 };
@@ -121,7 +122,7 @@ struct NewtonF64Args {
 };
 
 // Start of a batch solve: iterates from u0 (or 0), f(mu) (or the override), flags.
-__global__ void newton_init_kernel(NewtonF64Args a) {
+static __global__ void newton_init_kernel(NewtonF64Args a) {
   const int64_t Bp = a.s.Bp;
   const int NP = a.s.NP, N = a.N;
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < Bp * NP;
@@ -184,15 +185,22 @@ struct ContractArgs {
   double* J;               // Jacobian store [Bp][mp] or nullptr (pressure)
   int64_t mp;
   double* part;            // partial row sums [kSplit][Bp][ldp]
+  double* part2;           // second partial sums (kModeResid: J u) or nullptr
   int ldp;
 };
 
 __host__ __device__ inline int64_t contract_lds_bytes(int N, int R) {
-  return 8 * ((int64_t)kTile * N + (int64_t)kTile * R + kTile * (kMaxQ + kMaxQc));
+  return 8 * ((int64_t)kTile * N + 2 * (int64_t)kTile * R + kTile * (kMaxQ + kMaxQc));
 }
 
-template <bool kJac, int KT>
+// kMode: kModeJac (store J, fold A(mu)u), kModePressure (fold A_sv u + C_sv(u,u)),
+// kModeResid (fold A(mu)u into part and J u into part2; nothing stored) -- the FP64 residual
+// F(u) = (J u + A u)/2 - f of the mixed-precision refinement.
+constexpr int kModeJac = 0, kModePressure = 1, kModeResid = 2;
+
+template <int kMode, int KT>
 __global__ __launch_bounds__(kThreads) void contract_f64_kernel(ContractArgs a) {
+  constexpr bool kJac = kMode != kModePressure;     // affine fold + Newton flags
   extern __shared__ double smem[];
   const int N = a.N, R = a.R;
   const int kA = a.kA;                     // affine k-steps (1..3); tensor k-steps = KT
@@ -205,13 +213,17 @@ __global__ __launch_bounds__(kThreads) void contract_f64_kernel(ContractArgs a) 
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int split = blockIdx.x % kSplit;
   const int b0 = (blockIdx.x / kSplit) * kTile;
-  if (kJac && __syncthreads_and(tid < kTile ? a.done[b0 + tid] : 1)) return;
+  if (kJac && a.done && __syncthreads_and(tid < kTile ? a.done[b0 + tid] : 1)) return;
+  double* pl2 = tcl + kTile * kMaxQc;      // [kTile][R] J u (kModeResid only)
 
   for (int idx = tid; idx < kTile * N; idx += kThreads) {
     const int b = idx / N, l = idx - b * N, bg = b0 + b;
     ul[idx] = bg < a.B ? a.U[(int64_t)bg * a.ldU + l] : 0.0;
   }
-  for (int idx = tid; idx < kTile * R; idx += kThreads) pl[idx] = 0.0;
+  for (int idx = tid; idx < kTile * R; idx += kThreads) {
+    pl[idx] = 0.0;
+    if (kMode == kModeResid) pl2[idx] = 0.0;
+  }
   for (int idx = tid; idx < kTile * kMaxQ; idx += kThreads) {
     const int b = idx / kMaxQ, q = idx - b * kMaxQ, bg = b0 + b;
     tal[idx] = (bg < a.B && q < a.Q) ? a.ta[(int64_t)bg * a.Q + q] : 0.0;
@@ -278,7 +290,7 @@ __global__ __launch_bounds__(kThreads) void contract_f64_kernel(ContractArgs a) 
 
     // Accumulator layout of v_mfma_f64_16x16x4f64: lane l, element v = row l/16 + 4v,
     // column l%16 of the 16x16 tile. fold(): acc[m] * u_j into p_i for m = j*R + i.
-    auto fold = [&]() {
+    auto fold = [&](double* dst) {
       const int m0 = g0 * 16 + (lane >> 4);
       const int j0 = m0 / R, i0 = m0 - j0 * R;
 #pragma unroll
@@ -288,12 +300,12 @@ __global__ __launch_bounds__(kThreads) void contract_f64_kernel(ContractArgs a) 
           for (int v = 0; v < 4; ++v) {
             int i = i0 + 16 * r + 4 * v, j = j0;
             while (i >= R) { i -= R; ++j; }
-            if (j < N) atomicAdd(&pl[col * R + i], c[r][v] * ul[col * N + j]);
+            if (j < N) atomicAdd(&dst[col * R + i], c[r][v] * ul[col * N + j]);
           }
         }
       }
     };
-    if (kJac) fold();                      // affine part done: A(mu) u
+    if (kJac) fold(pl);                    // affine part done: A(mu) u
 
 #pragma unroll
     for (int ks = 0; ks < KT; ++ks) {
@@ -306,7 +318,7 @@ __global__ __launch_bounds__(kThreads) void contract_f64_kernel(ContractArgs a) 
         c[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[ks][r], wT[ks], c[r], 0, 0, 0);
     }
 
-    if (kJac) {
+    if (kMode == kModeJac) {
 #pragma unroll
       for (int r = 0; r < kGroup; ++r) {
         if (g0 + r < rb_hi) {
@@ -317,14 +329,17 @@ __global__ __launch_bounds__(kThreads) void contract_f64_kernel(ContractArgs a) 
           jp[12] = c[r][3];
         }
       }
+    } else if (kMode == kModeResid) {
+      fold(pl2);                           // J u
     } else {
-      fold();                              // A_sv u + C_sv(u,u)
+      fold(pl);                            // A_sv u + C_sv(u,u)
     }
   }
   __syncthreads();
   for (int idx = tid; idx < kTile * R; idx += kThreads) {
     const int b = idx / R, i = idx - b * R;
     a.part[((int64_t)split * a.Bp + b0 + b) * a.ldp + i] = pl[idx];
+    if (kMode == kModeResid) a.part2[((int64_t)split * a.Bp + b0 + b) * a.ldp + i] = pl2[idx];
   }
 }
 
@@ -394,7 +409,7 @@ __global__ __launch_bounds__(kThreads) void lu_f64_kernel(NewtonF64Args a, int i
   }
 }
 
-__global__ void newton_final_kernel(NewtonF64Args a) {
+static __global__ void newton_final_kernel(NewtonF64Args a) {
   const int NP = a.s.NP;
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < (int64_t)a.B * a.ldu;
        idx += (int64_t)gridDim.x * blockDim.x) {

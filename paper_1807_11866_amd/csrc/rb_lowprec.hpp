@@ -1,0 +1,352 @@
+// rb_lowprec.hpp -- mixed-precision Newton for gfx950: the Jacobian contraction from FP32 or
+// BF16 copies of the tensors on MFMA with FP32 accumulation, an FP32 register LU, iterates
+// and updates kept in FP64, and refinement steps whose residual F(u) = A(mu)u + C(mu)(u,u) - f
+// is evaluated from the FP64 tensors (kModeResid of the FP64 contraction).
+#pragma once
+
+#include <type_traits>
+
+#include "rb_kernels.hpp"
+
+namespace rb {
+
+typedef short bf16x8 __attribute__((ext_vector_type(8)));
+
+// FP64 -> BF16, round to nearest even, in one step (no intermediate FP32 rounding). Values
+// below the smallest normal BF16 flush to signed zero; overflow gives infinity.
+__host__ __device__ inline uint16_t f64_to_bf16(double x) {
+  uint64_t u;
+  __builtin_memcpy(&u, &x, 8);
+  const uint32_t sign = static_cast<uint32_t>(u >> 63) << 15;
+  const int e = static_cast<int>((u >> 52) & 0x7ff);
+  const uint64_t m = u & ((1ull << 52) - 1);
+  if (e == 0x7ff) return static_cast<uint16_t>(sign | 0x7f80 | (m ? 0x40 : 0));
+  int eb = e - 1023 + 127;
+  if (eb >= 255) return static_cast<uint16_t>(sign | 0x7f80);
+  if (eb <= 0) return static_cast<uint16_t>(sign);
+  uint64_t keep = m >> 45;
+  const uint64_t rest = m & ((1ull << 45) - 1), half = 1ull << 44;
+  if (rest > half || (rest == half && (keep & 1))) {
+    if (++keep == 128) {
+      keep = 0;
+      if (++eb >= 255) return static_cast<uint16_t>(sign | 0x7f80);
+    }
+  }
+  return static_cast<uint16_t>(sign | (static_cast<uint32_t>(eb) << 7) | keep);
+}
+
+// Low-precision packed solve operand, same rows (m = j*N + i) and column order as the FP64
+// one, in MFMA operand order:
+//   FP32 (v_mfma_f32_16x16x4f32): tile (rb, ks) = 64 floats, element e <-> (row rb*16 + e%16,
+//        k = ks*4 + e/16); affine part kA = ceil(Q/4) k-steps, tensor part KT k-steps.
+//   BF16 (v_mfma_f32_16x16x32_bf16): tile (rb, ks) = 64 lanes x 8 bf16, lane e holds row
+//        rb*16 + e%16, k = ks*32 + 8*(e/16) + t (t = 0..7); affine part 1 k-step (Q <= 32),
+//        tensor part KT = ceil(Qc*N/32) k-steps.
+template <bool kBF16>
+__global__ void pack_lp(const double* __restrict__ C, const double* __restrict__ A, int Nm, int N,
+                        int Q, int Qc, int kA, int nrb, int nks, void* __restrict__ out) {
+  constexpr int kK = kBF16 ? 32 : 4;        // k per k-step
+  const int64_t total = (int64_t)nrb * nks * 64 * (kBF16 ? 8 : 1);
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    int e, t;
+    int64_t tile;
+    if (kBF16) {
+      t = idx & 7;
+      e = (idx >> 3) & 63;
+      tile = idx >> 9;
+    } else {
+      t = 0;
+      e = idx & 63;
+      tile = idx >> 6;
+    }
+    const int rb = tile / nks, ks = tile % nks;
+    const int m = rb * 16 + (e & 15);
+    const int k = kBF16 ? ks * kK + 8 * (e >> 4) + t : ks * kK + (e >> 4);
+    double v = 0.0;
+    if (m < N * N) {
+      const int j = m / N, i = m - j * N;
+      if (k < kK * kA) {
+        if (k < Q) v = A[((int64_t)k * Nm + i) * Nm + j];
+      } else if (k - kK * kA < Qc * N) {
+        const int kk = k - kK * kA, q = kk / N, l = kk - q * N;
+        v = C[(((int64_t)q * Nm + i) * Nm + j) * Nm + l] + C[(((int64_t)q * Nm + i) * Nm + l) * Nm + j];
+      }
+    }
+    if (kBF16)
+      static_cast<uint16_t*>(out)[idx] = f64_to_bf16(v);
+    else
+      static_cast<float*>(out)[idx] = static_cast<float>(v);
+  }
+}
+
+struct ContractLpArgs {
+  const void* op;          // packed operand (float or bf16)
+  int nrb, kA, nks;        // row blocks, affine k-steps, k-steps per row block
+  int N, M, Q, Qc, B;
+  int64_t Bp;
+  const double* ta;
+  const double* tc;
+  const double* U;         // FP64 iterates [Bp][ldU]
+  int ldU;
+  const int* done;         // skip flags or nullptr
+  float* J;                // FP32 Jacobians [Bp][mp], column-major per request
+  int64_t mp;
+  float* part;             // partial A(mu) u [kSplit][Bp][ldp]
+  int ldp;
+};
+
+__host__ __device__ inline int64_t contract_lp_lds_bytes(int N) {
+  return 4 * (2 * (int64_t)kTile * N + kTile * (kMaxQ + kMaxQc));
+}
+
+// Same decomposition as contract_f64_kernel (64-request tile x row split per workgroup,
+// 16 requests and their W slice per wavefront, four row blocks per pass, static prefetch),
+// with FP32 (or BF16) operands and FP32 accumulators. Accumulator layout of the 16x16 FP32
+// MFMAs: lane l, element v = row 4*(l/16) + v, column l%16.
+template <bool kBF16, int KT>
+__global__ __launch_bounds__(kThreads) void contract_lp_kernel(ContractLpArgs a) {
+  extern __shared__ float smemf[];
+  typedef typename std::conditional<kBF16, bf16x8, float>::type opnd;
+  constexpr int kK = kBF16 ? 32 : 4;
+  constexpr int kAmax = kBF16 ? 1 : 3;
+  const int N = a.N;
+  float* ul = smemf;                       // [kTile][N]
+  float* pl = ul + kTile * N;              // [kTile][N]
+  float* tal = pl + kTile * N;             // [kTile][kMaxQ]
+  float* tcl = tal + kTile * kMaxQ;        // [kTile][kMaxQc]
+
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int split = blockIdx.x % kSplit;
+  const int b0 = (blockIdx.x / kSplit) * kTile;
+  if (a.done && __syncthreads_and(tid < kTile ? a.done[b0 + tid] : 1)) return;
+
+  for (int idx = tid; idx < kTile * N; idx += kThreads) {
+    const int b = idx / N, l = idx - b * N, bg = b0 + b;
+    ul[idx] = bg < a.B ? static_cast<float>(a.U[(int64_t)bg * a.ldU + l]) : 0.f;
+    pl[idx] = 0.f;
+  }
+  for (int idx = tid; idx < kTile * kMaxQ; idx += kThreads) {
+    const int b = idx / kMaxQ, q = idx - b * kMaxQ, bg = b0 + b;
+    tal[idx] = (bg < a.B && q < a.Q) ? static_cast<float>(a.ta[(int64_t)bg * a.Q + q]) : 0.f;
+  }
+  for (int idx = tid; idx < kTile * kMaxQc; idx += kThreads) {
+    const int b = idx / kMaxQc, q = idx - b * kMaxQc, bg = b0 + b;
+    tcl[idx] = (bg < a.B && q < a.Qc) ? static_cast<float>(a.tc[(int64_t)bg * a.Qc + q]) : 0.f;
+  }
+  __syncthreads();
+
+  // W column of this lane: request bl, k = ks*kK + (kBF16 ? 8*(lane/16) + t : lane/16).
+  const int bl = 16 * wv + (lane & 15);
+  auto wval = [&](int k) -> float {
+    if (k < kK * a.kA) return k < kMaxQ ? tal[bl * kMaxQ + k] : 0.f;
+    int l = k - kK * a.kA, q = 0;
+    while (l >= N && q < kMaxQc) { l -= N; ++q; }
+    return q < a.Qc ? tcl[bl * kMaxQc + q] * ul[bl * N + l] : 0.f;
+  };
+  opnd wA[kAmax], wT[KT];
+  auto make = [&](int ks) -> opnd {
+    if constexpr (kBF16) {
+      bf16x8 r;
+#pragma unroll
+      for (int t = 0; t < 8; ++t)
+        r[t] = static_cast<short>(f64_to_bf16(static_cast<double>(wval(ks * kK + 8 * (lane >> 4) + t))));
+      return r;
+    } else {
+      return wval(ks * kK + (lane >> 4));
+    }
+  };
+#pragma unroll
+  for (int ks = 0; ks < kAmax; ++ks) wA[ks] = make(ks);
+#pragma unroll
+  for (int ks = 0; ks < KT; ++ks) wT[ks] = make(a.kA + ks);
+
+  const int rb_lo = (int)((int64_t)split * a.nrb / kSplit);
+  const int rb_hi = (int)((int64_t)(split + 1) * a.nrb / kSplit);
+  const int col = bl;
+  const opnd* opb = static_cast<const opnd*>(a.op);
+
+  for (int g0 = rb_lo; g0 < rb_hi; g0 += kGroup) {
+    const opnd* opg[kGroup];
+#pragma unroll
+    for (int r = 0; r < kGroup; ++r)
+      opg[r] = opb + (int64_t)min(g0 + r, rb_hi - 1) * a.nks * 64 + lane;
+    opnd xa[kAmax][kGroup];
+#pragma unroll
+    for (int ks = 0; ks < kAmax; ++ks)
+#pragma unroll
+      for (int r = 0; r < kGroup; ++r) xa[ks][r] = opg[r][min(ks, a.kA - 1) * 64];
+    opnd x[KT][kGroup];
+#pragma unroll
+    for (int ks = 0; ks < kDepth && ks < KT; ++ks)
+#pragma unroll
+      for (int r = 0; r < kGroup; ++r) x[ks][r] = opg[r][(a.kA + ks) * 64];
+
+    auto mfma = [](opnd xx, opnd ww, f32x4 cc) -> f32x4 {
+      if constexpr (kBF16)
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(xx, ww, cc, 0, 0, 0);
+      else
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(xx, ww, cc, 0, 0, 0);
+    };
+    f32x4 c[kGroup];
+#pragma unroll
+    for (int r = 0; r < kGroup; ++r) c[r] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < kAmax; ++ks) {
+      if (ks < a.kA) {
+#pragma unroll
+        for (int r = 0; r < kGroup; ++r) c[r] = mfma(xa[ks][r], wA[ks], c[r]);
+      }
+    }
+    // fold A(mu) rows: acc[m] * u_j into p_i (m = j*N + i)
+    {
+      const int m0 = g0 * 16 + 4 * (lane >> 4);
+      const int j0 = m0 / N, i0 = m0 - j0 * N;
+#pragma unroll
+      for (int r = 0; r < kGroup; ++r) {
+        if (g0 + r < rb_hi) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            int i = i0 + 16 * r + v, j = j0;
+            while (i >= N) { i -= N; ++j; }
+            if (j < N) atomicAdd(&pl[col * N + i], c[r][v] * ul[col * N + j]);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int ks = 0; ks < KT; ++ks) {
+      if (ks + kDepth < KT) {
+#pragma unroll
+        for (int r = 0; r < kGroup; ++r) x[ks + kDepth][r] = opg[r][(a.kA + ks + kDepth) * 64];
+      }
+#pragma unroll
+      for (int r = 0; r < kGroup; ++r) c[r] = mfma(x[ks][r], wT[ks], c[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < kGroup; ++r) {
+      if (g0 + r < rb_hi) {
+        float* jp = a.J + (int64_t)(b0 + col) * a.mp + (g0 + r) * 16 + 4 * (lane >> 4);
+        *reinterpret_cast<f32x4*>(jp) = c[r];
+      }
+    }
+  }
+  __syncthreads();
+  for (int idx = tid; idx < kTile * N; idx += kThreads) {
+    const int b = idx / N, i = idx - b * N;
+    a.part[((int64_t)split * a.Bp + b0 + b) * a.ldp + i] = pl[idx];
+  }
+}
+
+struct LpNewtonArgs {
+  int N, Nm, B;
+  double tol;              // stopping test ||delta||_H <= tol ||u||_H
+  double stag;             // low-precision phase: stagnation counts below stag ||u||_H
+  const double* H;         // [Nm][Nm] norm Gram or nullptr
+  const float* J;          // [Bp][mp]
+  int64_t mp;
+  const float* part;       // [kSplit][Bp][NP] A(mu) u (FP32 iteration)
+  const double* partA;     // [kSplit][Bp][NP] A(mu) u (FP64 refinement)
+  const double* partJ;     // [kSplit][Bp][NP] J(u) u (FP64 refinement)
+  NewtonState s;           // FP64 iterates, f, flags
+};
+
+// One wavefront per request. Low-precision phase (kRefine = false): F(u) ~ (J u + A u)/2 - f
+// from the FP32 / BF16 contraction, a request stops when its update is below tol or has
+// stagnated (below stag and no longer halving). Refinement (kRefine = true): F(u) =
+// (J u + A u)/2 - f from the FP64 contraction with the Jacobian of the last low-precision
+// step. Either way the correction solves J32 delta = -F(u) by the FP32 register LU and is
+// added to the FP64 iterate.
+template <int NP, bool kRefine>
+__global__ __launch_bounds__(kThreads) void lu_lp_kernel(LpNewtonArgs a, int it) {
+  __shared__ float prow[kWaves][NP + 8];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int b = blockIdx.x * kWaves + wv;
+  if (b >= a.B || a.s.done[b]) return;
+  const int N = a.N;
+  const int64_t Bp = a.s.Bp;
+  const float* jb = a.J + (int64_t)b * a.mp;
+  const double* ub = a.s.U + (int64_t)b * NP;
+  float r[NP];
+  const int lc = lane < N ? lane : N - 1;
+  bool bad = false;
+  double rhs64 = 0.0;
+  float ju = 0.f;
+#pragma unroll
+  for (int c = 0; c < NP; ++c) {
+    const float v = jb[(c < N ? c : N - 1) * N + lc];
+    r[c] = (c < N && lane < N) ? v : (c == lane ? 1.f : 0.f);
+    ju = fmaf(r[c], static_cast<float>(ub[c]), ju);
+    bad |= !finite_val(r[c]);
+  }
+  if (lane < N) {
+    if (kRefine) {
+      double au = 0.0, jv = 0.0;
+#pragma unroll
+      for (int sp = 0; sp < kSplit; ++sp) {
+        au += a.partA[((int64_t)sp * Bp + b) * NP + lane];
+        jv += a.partJ[((int64_t)sp * Bp + b) * NP + lane];
+      }
+      rhs64 = -(0.5 * (jv + au) - a.s.Fv[(int64_t)b * NP + lane]);
+    } else {
+      float au = 0.f;
+#pragma unroll
+      for (int sp = 0; sp < kSplit; ++sp) au += a.part[((int64_t)sp * Bp + b) * NP + lane];
+      rhs64 = -(0.5 * (static_cast<double>(ju) + au) - a.s.Fv[(int64_t)b * NP + lane]);
+    }
+  }
+  float rhs = static_cast<float>(rhs64);
+  bad |= !finite_val(rhs);
+  int flag = __builtin_amdgcn_readfirstlane(__any(bad) ? 3 : 0);
+  float dxf = 0.f;
+  if (flag == 0) flag = lu_solve_rows<NP, false>(r, rhs, lane, &prow[wv][0], dxf);
+  if (flag == 0) {
+    const double dx = lane < N ? static_cast<double>(dxf) : 0.0;
+    const double un = (lane < N ? ub[lane] : 0.0) + dx;
+    double hd = dx, hu = un;
+    if (a.H) {
+      hd = 0.0;
+      hu = 0.0;
+      for (int c = 0; c < N; ++c) {
+        const double h = a.H[(int64_t)c * a.Nm + lc];
+        hd = fma(h, bcast(dx, c), hd);
+        hu = fma(h, bcast(un, c), hu);
+      }
+    }
+    if (lane >= N) { hd = 0.0; hu = 0.0; }
+    const double nd2 = wave_sum(dx * hd), nu2 = wave_sum(un * hu);
+    if (!finite_val(nd2) || !finite_val(nu2)) flag = 3;
+    if (flag == 0) {
+      if (lane < N) a.s.U[(int64_t)b * NP + lane] = un;
+      if (lane == 0) {
+        a.s.iters[b] = a.s.iters[b] + 1;
+        const double nd = sqrt(nd2), nu = sqrt(nu2);
+        if (nd <= a.tol * nu) {
+          a.s.status[b] = 0;
+          a.s.done[b] = 1;
+        } else if (!kRefine && it > 0 && nd <= a.stag * nu && nd > 0.5 * a.s.dprev[b]) {
+          a.s.done[b] = 1;                 // stagnated: status stays RB_ST_MAXIT
+        }
+        if (!kRefine) a.s.dprev[b] = nd;
+      }
+    }
+  }
+  if (flag != 0 && lane == 0) {
+    a.s.status[b] = flag;
+    a.s.done[b] = 1;
+  }
+}
+
+// Between the phases: every request without a failure status is refined (status back to
+// RB_ST_MAXIT until a refinement update meets the tolerance).
+static __global__ void lp_refine_reset_kernel(int B, int64_t Bp, int* done, int* status) {
+  for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < Bp;
+       b += (int64_t)gridDim.x * blockDim.x) {
+    if (b >= B) { done[b] = 1; continue; }
+    const int s = status[b];
+    done[b] = s >= 2;
+    if (s < 2) status[b] = 1;
+  }
+}
+
+}  // namespace rb

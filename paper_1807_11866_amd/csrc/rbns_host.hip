@@ -14,7 +14,7 @@
 #include <vector>
 
 #include "../../include/rbns.h"
-#include "rb_kernels.hpp"
+#include "rb_launch.hpp"
 
 namespace {
 
@@ -55,6 +55,7 @@ struct Set {
   bool hasH = false;
   std::map<int, Pack> solve_f64;                     // key: N
   std::map<std::pair<int, int>, Pack> press_f64;     // key: (N, Np)
+  std::map<std::pair<int, int>, Pack> solve_lp;      // key: (N, 0 = FP32 | 1 = BF16)
 };
 
 struct Workspace {
@@ -175,30 +176,40 @@ int press_pack_f64(rb_ctx* c, Set* s, int N, int Np, Pack** out) {
   return RB_OK;
 }
 
-// Launch the contraction kernel instantiated for the operand's tensor k-step count.
-template <bool kJac, int KT>
-int launch_contract_kt(const rb::ContractArgs& g, hipStream_t st) {
-  const size_t lds = (size_t)rb::contract_lds_bytes(g.N, g.R);
-  if (lds > 64 * 1024)
-    HIP_TRY(hipFuncSetAttribute((const void*)rb::contract_f64_kernel<kJac, KT>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  const int grid = (int)(g.Bp / rb::kTile) * rb::kSplit;
-  hipLaunchKernelGGL((rb::contract_f64_kernel<kJac, KT>), dim3(grid), dim3(rb::kThreads), lds,
-                     st, g);
+// Mixed-precision packed operand for basis size N (FP32 or BF16 copy of the FP64 tensors).
+int lp_tensor_ksteps(int Qc, int N, bool bf16) {
+  return bf16 ? (int)(ceil_to((int64_t)Qc * N, 32) / 32) : tensor_ksteps(Qc, N);
+}
+
+int solve_pack_lp(rb_ctx* c, Set* s, int N, bool bf16, Pack** out) {
+  auto key = std::make_pair(N, bf16 ? 1 : 0);
+  auto it = s->solve_lp.find(key);
+  if (it != s->solve_lp.end()) { *out = &it->second; return RB_OK; }
+  Pack p;
+  p.nrb = (int)(ceil_to((int64_t)N * N, 16) / 16);
+  p.nks_s = bf16 ? 1 : affine_ksteps(s->Q);
+  p.nks = p.nks_s + lp_tensor_ksteps(s->Qc, N, bf16);
+  const int64_t total = (int64_t)p.nrb * p.nks * 64 * (bf16 ? 8 : 1);
+  int rc = dev_alloc(c, p.buf, total * (bf16 ? 2 : 4));
+  if (rc) return rc;
+  if (bf16)
+    hipLaunchKernelGGL(rb::pack_lp<true>, dim3(launch_grid(total)), dim3(256), 0, 0,
+                       (const double*)s->C.p, (const double*)s->A.p, s->N, N, s->Q, s->Qc,
+                       p.nks_s, p.nrb, p.nks, p.buf.p);
+  else
+    hipLaunchKernelGGL(rb::pack_lp<false>, dim3(launch_grid(total)), dim3(256), 0, 0,
+                       (const double*)s->C.p, (const double*)s->A.p, s->N, N, s->Q, s->Qc,
+                       p.nks_s, p.nrb, p.nks, p.buf.p);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipDeviceSynchronize());
+  *out = &s->solve_lp.emplace(key, p).first->second;
   return RB_OK;
 }
 
-template <bool kJac>
-int launch_contract(const rb::ContractArgs& g, hipStream_t st) {
-  switch (g.nks - g.kA) {
-#define RB_KT(n) case n: return launch_contract_kt<kJac, n>(g, st);
-    RB_KT(2) RB_KT(4) RB_KT(6) RB_KT(8) RB_KT(10) RB_KT(12) RB_KT(14) RB_KT(16) RB_KT(18)
-    RB_KT(20) RB_KT(22) RB_KT(24) RB_KT(26) RB_KT(28) RB_KT(30) RB_KT(32) RB_KT(34) RB_KT(36)
-    RB_KT(38) RB_KT(40) RB_KT(42) RB_KT(44) RB_KT(46) RB_KT(48) RB_KT(50) RB_KT(52) RB_KT(54)
-    RB_KT(56) RB_KT(58) RB_KT(60) RB_KT(62) RB_KT(64)
-#undef RB_KT
-  }
-  return fail(RB_E_UNSUPPORTED, "contraction with %d tensor k-steps not built", g.nks - g.kA);
+int launch_rc(int rc, const char* what) {
+  if (rc == 0) return RB_OK;
+  if (rc == -5) return fail(RB_E_UNSUPPORTED, "%s: size not built", what);
+  return fail(RB_E_DEVICE, "%s: launch failed: %s", what, hipGetErrorString(hipGetLastError()));
 }
 
 int workspace(rb_ctx* c, void* stream, size_t bytes, Workspace** out) {
@@ -218,7 +229,7 @@ int workspace(rb_ctx* c, void* stream, size_t bytes, Workspace** out) {
 
 // Carve the Newton state for Bp (padded) requests out of one workspace allocation.
 size_t newton_state_bytes(int64_t Bp, int NP, int64_t mp) {
-  return (size_t)(Bp * mp + (2 + rb::kSplit) * Bp * NP) * sizeof(double) +
+  return (size_t)(Bp * mp + (2 + rb::kSplit) * Bp * NP + Bp) * sizeof(double) +
          (size_t)3 * Bp * sizeof(int) + 256;
 }
 
@@ -233,6 +244,8 @@ rb::NewtonState carve_state(void* base, int64_t Bp, int NP, int64_t mp) {
   d += Bp * NP;
   s.Wv = d;
   d += rb::kSplit * Bp * NP;
+  s.dprev = d;
+  d += Bp;
   int* ip = (int*)d;
   s.done = ip;
   s.iters = ip + Bp;
@@ -245,8 +258,8 @@ rb::NewtonState carve_state(void* base, int64_t Bp, int NP, int64_t mp) {
 
 int np_bucket(int n) { return (int)ceil_to(n, 4); }
 
-enum { FAM_JACOBIAN = 0, FAM_LU = 1, FAM_PRESSURE = 2, FAM_COUNT = 3 };
-const char* const kFamilies[FAM_COUNT] = {"jacobian", "lu", "pressure"};
+enum { FAM_JACOBIAN = 0, FAM_LU = 1, FAM_PRESSURE = 2, FAM_RESIDUAL = 3, FAM_COUNT = 4 };
+const char* const kFamilies[FAM_COUNT] = {"jacobian", "lu", "pressure", "residual"};
 
 hipEvent_t take_event(rb_ctx* c) {
   if (!c->event_pool.empty()) {
@@ -280,38 +293,6 @@ struct LaunchTimer {
   }
 };
 
-template <int NP>
-int launch_lu(const rb::NewtonF64Args& a, int it, bool lds, hipStream_t st) {
-  const dim3 grid((a.B + rb::kWaves - 1) / rb::kWaves);
-  if (lds)
-    hipLaunchKernelGGL((rb::lu_f64_kernel<NP, true>), grid, dim3(rb::kThreads), 0, st, a, it);
-  else
-    hipLaunchKernelGGL((rb::lu_f64_kernel<NP, false>), grid, dim3(rb::kThreads), 0, st, a, it);
-  return RB_OK;
-}
-
-int dispatch_lu(int NP, const rb::NewtonF64Args& a, int it, bool lds, hipStream_t st) {
-  switch (NP) {
-    case 4: return launch_lu<4>(a, it, lds, st);
-    case 8: return launch_lu<8>(a, it, lds, st);
-    case 12: return launch_lu<12>(a, it, lds, st);
-    case 16: return launch_lu<16>(a, it, lds, st);
-    case 20: return launch_lu<20>(a, it, lds, st);
-    case 24: return launch_lu<24>(a, it, lds, st);
-    case 28: return launch_lu<28>(a, it, lds, st);
-    case 32: return launch_lu<32>(a, it, lds, st);
-    case 36: return launch_lu<36>(a, it, lds, st);
-    case 40: return launch_lu<40>(a, it, lds, st);
-    case 44: return launch_lu<44>(a, it, lds, st);
-    case 48: return launch_lu<48>(a, it, lds, st);
-    case 52: return launch_lu<52>(a, it, lds, st);
-    case 56: return launch_lu<56>(a, it, lds, st);
-    case 60: return launch_lu<60>(a, it, lds, st);
-    case 64: return launch_lu<64>(a, it, lds, st);
-  }
-  return fail(RB_E_UNSUPPORTED, "basis size bucket %d not built", NP);
-}
-
 // Enqueue a whole batched Newton solve: init, max_iter x (Jacobian kernel, LU kernel),
 // final copy-out. Converged requests are skipped by both kernels through the done flags.
 int enqueue_newton(rb_ctx* c, const rb::NewtonF64Args& a, hipStream_t st) {
@@ -326,15 +307,15 @@ int enqueue_newton(rb_ctx* c, const rb::NewtonF64Args& a, hipStream_t st) {
   g.U = a.s.U; g.ldU = NP;
   g.done = a.s.done;
   g.J = a.s.J; g.mp = a.s.mp;
-  g.part = a.s.Wv; g.ldp = NP;
+  g.part = a.s.Wv; g.part2 = nullptr; g.ldp = NP;
   hipLaunchKernelGGL(rb::newton_init_kernel, dim3(launch_grid(Bp * NP)), dim3(256), 0, st, a);
   for (int it = 0; it < a.maxit; ++it) {
     {
       LaunchTimer t(c, FAM_JACOBIAN, st);
-      if (int rc = launch_contract<true>(g, st)) return rc;
+      if (int rc = launch_rc(rb::launch::contract_f64(rb::kModeJac, g, st), "jacobian")) return rc;
     }
     LaunchTimer t(c, FAM_LU, st);
-    if (int rc = dispatch_lu(NP, a, it, c->lu_lds, st)) return rc;
+    if (int rc = launch_rc(rb::launch::lu_f64(NP, a, it, c->lu_lds, st), "lu")) return rc;
   }
   hipLaunchKernelGGL(rb::newton_final_kernel, dim3(launch_grid((int64_t)a.B * a.ldu)),
                      dim3(256), 0, st, a);
@@ -342,36 +323,81 @@ int enqueue_newton(rb_ctx* c, const rb::NewtonF64Args& a, hipStream_t st) {
   return RB_OK;
 }
 
-template <int NPP>
-int launch_plu(const rb::PressureF64Args& a, bool lds, hipStream_t st) {
-  const dim3 grid((a.B + rb::kWaves - 1) / rb::kWaves);
-  if (lds)
-    hipLaunchKernelGGL((rb::plu_f64_kernel<NPP, true>), grid, dim3(rb::kThreads), 0, st, a);
-  else
-    hipLaunchKernelGGL((rb::plu_f64_kernel<NPP, false>), grid, dim3(rb::kThreads), 0, st, a);
+// Mixed-precision batched Newton: the low-precision phase (FP32 or BF16 contraction, FP32
+// LU, FP64 iterates) until each request's update is below tol or has stagnated, then up to
+// refine_steps refinement steps, each with the FP64 residual and the Jacobian of the last
+// low-precision step, until the update is below tol.
+int enqueue_newton_lp(rb_ctx* c, Set* s, const rb::NewtonF64Args& a, bool bf16, int refine,
+                      Workspace* w, hipStream_t st) {
+  const int N = a.N, NP = a.s.NP;
+  const int64_t Bp = a.s.Bp, mp = a.s.mp;
+  Pack *pf, *pl;
+  if (int rc = solve_pack_f64(c, s, N, &pf)) return rc;
+  if (int rc = solve_pack_lp(c, s, N, bf16, &pl)) return rc;
+  // low-precision buffers follow the FP64 state in the workspace
+  char* base = (char*)w->buf.p + newton_state_bytes(Bp, NP, mp);
+  float* J32 = (float*)base;
+  float* part32 = J32 + Bp * mp;
+  double* partA = (double*)(part32 + rb::kSplit * Bp * NP + 64);
+  partA = (double*)(((uintptr_t)partA + 255) & ~(uintptr_t)255);
+  double* partJ = partA + rb::kSplit * Bp * NP;
+
+  rb::ContractLpArgs gl;
+  gl.op = pl->buf.p;
+  gl.nrb = pl->nrb; gl.kA = pl->nks_s; gl.nks = pl->nks;
+  gl.N = N; gl.M = N * N; gl.Q = a.Q; gl.Qc = a.Qc; gl.B = a.B; gl.Bp = Bp;
+  gl.ta = a.ta; gl.tc = a.tc; gl.U = a.s.U; gl.ldU = NP;
+  gl.done = a.s.done;
+  gl.J = J32; gl.mp = mp;
+  gl.part = part32; gl.ldp = NP;
+  const int KT = pl->nks - pl->nks_s;
+
+  rb::ContractArgs gr;                      // FP64 residual
+  gr.op = (const double*)pf->buf.p;
+  gr.nrb = pf->nrb; gr.nks = pf->nks; gr.kA = pf->nks_s;
+  gr.R = N; gr.N = N; gr.M = N * N;
+  gr.Q = a.Q; gr.Qc = a.Qc; gr.B = a.B; gr.Bp = Bp;
+  gr.ta = a.ta; gr.tc = a.tc; gr.U = a.s.U; gr.ldU = NP;
+  gr.done = a.s.done; gr.J = nullptr; gr.mp = 0;
+  gr.part = partA; gr.part2 = partJ; gr.ldp = NP;
+
+  rb::LpNewtonArgs la;
+  la.N = N; la.Nm = a.Nm; la.B = a.B;
+  la.tol = a.tol; la.H = a.H;
+  la.stag = bf16 ? 5e-2 : 1e-3;
+  la.J = J32; la.mp = mp; la.part = part32; la.partA = partA; la.partJ = partJ;
+  la.s = a.s;
+
+  hipLaunchKernelGGL(rb::newton_init_kernel, dim3(launch_grid(Bp * NP)), dim3(256), 0, st, a);
+  for (int it = 0; it < a.maxit; ++it) {
+    {
+      LaunchTimer t(c, FAM_JACOBIAN, st);
+      if (int rc = launch_rc(rb::launch::contract_lp(bf16, KT, gl, st), "lp jacobian")) return rc;
+    }
+    LaunchTimer t(c, FAM_LU, st);
+    if (int rc = launch_rc(rb::launch::lu_lp(NP, false, la, it, st), "lp lu")) return rc;
+  }
+  if (refine > 0)
+    hipLaunchKernelGGL(rb::lp_refine_reset_kernel, dim3(launch_grid(Bp)), dim3(256), 0, st,
+                       a.B, Bp, a.s.done, a.s.status);
+  for (int r = 0; r < refine; ++r) {
+    {
+      LaunchTimer t(c, FAM_RESIDUAL, st);
+      if (int rc = launch_rc(rb::launch::contract_f64(rb::kModeResid, gr, st), "fp64 residual"))
+        return rc;
+    }
+    LaunchTimer t(c, FAM_LU, st);
+    if (int rc = launch_rc(rb::launch::lu_lp(NP, true, la, a.maxit + r, st), "lp refine")) return rc;
+  }
+  hipLaunchKernelGGL(rb::newton_final_kernel, dim3(launch_grid((int64_t)a.B * a.ldu)),
+                     dim3(256), 0, st, a);
+  HIP_TRY(hipGetLastError());
   return RB_OK;
 }
 
-int dispatch_plu(int NPP, const rb::PressureF64Args& a, bool lds, hipStream_t st) {
-  switch (NPP) {
-    case 4: return launch_plu<4>(a, lds, st);
-    case 8: return launch_plu<8>(a, lds, st);
-    case 12: return launch_plu<12>(a, lds, st);
-    case 16: return launch_plu<16>(a, lds, st);
-    case 20: return launch_plu<20>(a, lds, st);
-    case 24: return launch_plu<24>(a, lds, st);
-    case 28: return launch_plu<28>(a, lds, st);
-    case 32: return launch_plu<32>(a, lds, st);
-    case 36: return launch_plu<36>(a, lds, st);
-    case 40: return launch_plu<40>(a, lds, st);
-    case 44: return launch_plu<44>(a, lds, st);
-    case 48: return launch_plu<48>(a, lds, st);
-    case 52: return launch_plu<52>(a, lds, st);
-    case 56: return launch_plu<56>(a, lds, st);
-    case 60: return launch_plu<60>(a, lds, st);
-    case 64: return launch_plu<64>(a, lds, st);
-  }
-  return fail(RB_E_UNSUPPORTED, "pressure size bucket %d not built", NPP);
+size_t lp_extra_bytes(int64_t Bp, int NP, int64_t mp) {
+  return (size_t)(Bp * mp + rb::kSplit * Bp * NP + 64) * sizeof(float) + 512 +
+         (size_t)2 * rb::kSplit * Bp * NP * sizeof(double);
 }
 
 }  // namespace
@@ -406,6 +432,7 @@ int rb_destroy(rb_ctx* c) {
     for (DevBuf* b : {&s.A, &s.C, &s.F, &s.H, &s.BpT, &s.Asv, &s.Csv, &s.Fs}) dev_free(c, *b);
     for (auto& kv : s.solve_f64) dev_free(c, kv.second.buf);
     for (auto& kv : s.press_f64) dev_free(c, kv.second.buf);
+    for (auto& kv : s.solve_lp) dev_free(c, kv.second.buf);
   }
   for (auto& kv : c->ws) dev_free(c, kv.second.buf);
   for (auto& t : c->timed) {
@@ -503,8 +530,10 @@ int rb_solve_batch(rb_ctx* c, int set, int B, int N, int ldu, const double* ta,
   if (!(o.tol >= 0.0) || o.max_iter < 1 || o.max_iter > 1000)
     return fail(RB_E_INVAL, "rb_solve_batch: bad options (tol=%g, max_iter=%d)", o.tol,
                 o.max_iter);
-  if (o.precision != RB_PREC_F64)
-    return fail(RB_E_UNSUPPORTED, "rb_solve_batch: precision %d not available", o.precision);
+  if (o.precision != RB_PREC_F64 && o.precision != RB_PREC_F32 && o.precision != RB_PREC_BF16)
+    return fail(RB_E_INVAL, "rb_solve_batch: unknown precision %d", o.precision);
+  if (o.precision != RB_PREC_F64 && (o.refine_steps < 0 || o.refine_steps > 100))
+    return fail(RB_E_INVAL, "rb_solve_batch: refine_steps=%d", o.refine_steps);
   if (B == 0) return RB_OK;
   if (!ta || !tc || (!tf && !fover) || !u || !iters || !status)
     return fail(RB_E_INVAL, "rb_solve_batch: NULL array");
@@ -516,7 +545,9 @@ int rb_solve_batch(rb_ctx* c, int set, int B, int N, int ldu, const double* ta,
   const int NP = np_bucket(N);
   const int64_t Bp = ceil_to(B, rb::kTile);
   Workspace* w;
-  if (int rc = workspace(c, stream, newton_state_bytes(Bp, NP, mp), &w)) return rc;
+  size_t ws = newton_state_bytes(Bp, NP, mp);
+  if (o.precision != RB_PREC_F64) ws += lp_extra_bytes(Bp, NP, mp);
+  if (int rc = workspace(c, stream, ws, &w)) return rc;
   rb::NewtonF64Args a;
   a.op = (const double*)pk->buf.p;
   a.nrb = pk->nrb; a.nks_s = pk->nks_s; a.nks = pk->nks;
@@ -527,7 +558,9 @@ int rb_solve_batch(rb_ctx* c, int set, int B, int N, int ldu, const double* ta,
   a.H = s->hasH ? (const double*)s->H.p : nullptr;
   a.u = u; a.iters = iters; a.status = status;
   a.s = carve_state(w->buf.p, Bp, NP, mp);
-  return enqueue_newton(c, a, (hipStream_t)stream);
+  if (o.precision == RB_PREC_F64) return enqueue_newton(c, a, (hipStream_t)stream);
+  return enqueue_newton_lp(c, s, a, o.precision == RB_PREC_BF16, o.refine_steps, w,
+                           (hipStream_t)stream);
 }
 
 int rb_solve_uneven(rb_ctx* c, int, int, const int*, int, const double*, const double*,
@@ -571,7 +604,7 @@ int rb_recover_pressure(rb_ctx* c, int set, int B, int N, int Np, int ldu, int l
   g.U = u; g.ldU = ldu;
   g.done = nullptr;
   g.J = nullptr; g.mp = 0;
-  g.part = (double*)w->buf.p; g.ldp = NPP;
+  g.part = (double*)w->buf.p; g.part2 = nullptr; g.ldp = NPP;
   rb::PressureF64Args a;
   a.Np = Np; a.Npm = s->Np; a.Qf = s->Qf; a.Qb = s->Qb; a.B = B; a.ldp = ldp; a.Bp = Bp;
   a.tf = tf; a.tb = tb;
@@ -580,8 +613,9 @@ int rb_recover_pressure(rb_ctx* c, int set, int B, int N, int Np, int ldu, int l
   a.part = g.part;
   a.p = p; a.status = status;
   LaunchTimer t(c, FAM_PRESSURE, st);
-  if (int rc = launch_contract<false>(g, st)) return rc;
-  if (int rc = dispatch_plu(NPP, a, c->lu_lds, st)) return rc;
+  if (int rc = launch_rc(rb::launch::contract_f64(rb::kModePressure, g, st), "pressure"))
+    return rc;
+  if (int rc = launch_rc(rb::launch::plu_f64(NPP, a, c->lu_lds, st), "pressure lu")) return rc;
   HIP_TRY(hipGetLastError());
   return RB_OK;
 }

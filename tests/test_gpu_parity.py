@@ -216,6 +216,87 @@ def test_stokes_limit_on_gpu(R, c2):
     s.close()
 
 
+# ------------------------------------------------------------- mixed precision ----
+# Low-precision Newton (FP32 or BF16 tensors on MFMA, FP32 LU, FP64 iterates) followed by
+# refinement steps with the FP64 residual: the result must reach the FP64 oracle within 1e-8.
+
+TOL_MIXED = 1e-8
+
+
+def _mixed(R, s, th, prec, refine, tol=1e-12, max_iter=10):
+    out = s.solve(th, precision=getattr(R, "RB_PREC_" + prec), refine_steps=refine, tol=tol,
+                  max_iter=max_iter)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+@pytest.mark.parametrize("prec,refine", [("F32", 1), ("BF16", 3)])
+def test_mixed_precision_parity_ragged(O, R, c2, prec, refine):
+    mu = draw_mu(get_config("batched_n50"), 300, seed_offset=11)
+    s = R.Solver(c2)
+    th = s.theta(_dev(mu))
+    g = _mixed(R, s, th, prec, refine)
+    r = O.solve_batch(O.OracleSet(c2), mu)
+    assert np.all(g["status"] <= 1)
+    err = _rel(g["u"], r["u"])
+    assert np.max(err) <= TOL_MIXED, (np.max(err), np.percentile(err, 99))
+    s.close()
+
+
+def test_mixed_refinement_contracts_error(O, R, c2):
+    """Each FP64-residual step shrinks the BF16 error by a factor of ten or more (the
+    low-precision Jacobian's relative error times the conditioning is well below 0.1)."""
+    mu = draw_mu(get_config("batched_n50"), 64, seed_offset=5)
+    s = R.Solver(c2)
+    th = s.theta(_dev(mu))
+    r = O.solve_batch(O.OracleSet(c2), mu)
+    errs = [np.max(_rel(_mixed(R, s, th, "BF16", k)["u"], r["u"])) for k in range(4)]
+    assert errs[0] <= 1e-2
+    for e0, e1 in zip(errs, errs[1:]):
+        assert e1 <= 0.1 * e0 or e1 <= 1e-13, errs
+    s.close()
+
+
+def test_mixed_converges_to_fp64_tolerance(O, R, c2):
+    mu = draw_mu(get_config("batched_n50"), 100, seed_offset=7)
+    s = R.Solver(c2)
+    th = s.theta(_dev(mu))
+    r = O.solve_batch(O.OracleSet(c2), mu)
+    for prec in ("F32", "BF16"):
+        g = _mixed(R, s, th, prec, 12)
+        assert np.all(g["status"] == 0), prec
+        assert np.max(_rel(g["u"], r["u"])) <= 1e-12, prec
+    s.close()
+
+
+@pytest.mark.parametrize("N", [1, 9, 33, 64])
+def test_mixed_random_tensors(O, R, N):
+    ts = _random_set(N, seed=100 + N)
+    mu = np.column_stack([np.linspace(0.0, 0.6, 21), np.linspace(100, 1000, 21)])
+    s = R.Solver(ts)
+    th = s.theta(_dev(mu))
+    r = O.solve_batch(O.OracleSet(ts), mu, maxit=20)
+    for prec, refine in (("F32", 2), ("BF16", 6)):
+        g = _mixed(R, s, th, prec, refine, max_iter=20)
+        assert np.all(g["status"] <= 1), prec
+        assert np.max(_rel(g["u"], r["u"])) <= TOL_MIXED, prec
+    s.close()
+
+
+def test_mixed_status_codes(R, c1):
+    s = R.Solver(c1)
+    mu = np.tile([[0.2, 300.0]], (3, 1))
+    th = s.theta(_dev(mu))
+    th["ta"][1].zero_()
+    th["tc"][1].zero_()
+    th["ta"][2, 0] = float("nan")
+    for prec in ("F32", "BF16"):
+        g = _mixed(R, s, th, prec, 2)
+        assert list(g["status"][1:]) == [2, 3], prec
+        assert list(g["iters"][1:]) == [0, 0], prec
+    s.close()
+
+
 # ------------------------------------------------------------- statuses and errors ---
 
 def test_status_codes_forced_from_host(R, c1):
