@@ -91,9 +91,11 @@ typedef struct {
                             to the FP64 iterate                                              */
 } rb_solve_opts;
 
-/* Size limits of this build (the LU keeps one system row per lane of a 64-wide wavefront). */
-#define RB_MAX_N   64
-#define RB_MAX_NP  64
+/* Size limits of this build. The LU keeps one system row per lane: one 64-wide wavefront per
+ * system up to 64 unknowns, a workgroup of ceil(N/64) wavefronts beyond. */
+#define RB_MAX_N      152   /* basis size, mixed precisions (FP32 LU)                   */
+#define RB_MAX_N_F64   96   /* basis size, RB_PREC_F64 (FP64 LU rows in registers)      */
+#define RB_MAX_NP      64   /* pressure basis size                                      */
 #define RB_MAX_Q   12
 #define RB_MAX_QC   4
 #define RB_MAX_QF   2
@@ -152,7 +154,7 @@ int rb_theta(rb_ctx *ctx, int set, int B, const double *mu, double *theta_a, dou
  * step) until an update is below tol (status RB_ST_CONVERGED, else RB_ST_MAXIT). iters
  * counts both kinds of updates.
  * Errors: RB_E_INVAL (NULL, B < 0, N or ldu out of range, bad opts), RB_E_NOMEM,
- * RB_E_UNSUPPORTED, RB_E_DEVICE. B == 0 is a no-op.
+ * RB_E_UNSUPPORTED (RB_PREC_F64 with N > RB_MAX_N_F64), RB_E_DEVICE. B == 0 is a no-op.
  */
 int rb_solve_batch(rb_ctx *ctx, int set, int B, int N, int ldu, const double *theta_a,
                    const double *theta_c, const double *theta_f, const double *f_override,

@@ -196,3 +196,176 @@ __device__ __forceinline__ int lu_solve_rows(T (&a)[NP], T rhs, int lane, T* pro
 }
 
 }  // namespace rb
+
+namespace rb {
+
+// LDS scratch of gj_solve_mw for one system: candidate rows (double-buffered by step
+// parity), candidate values and positions, and the solution vector.
+template <int NP, int W, typename T>
+struct GjShared {
+  static constexpr int kRow = (NP + 1 + 3) & ~3;   // pivot row + right-hand side, padded
+  T rows[2][W][kRow];
+  T cv[2][W];
+  int cp[2][W];
+  T xs[NP];
+  double red[W][2];
+};
+
+// Dense solve of one NP x NP system spread over the W wavefronts of a workgroup, one row
+// per lane (row = 64*wave + lane; rows >= NP hold nothing), by Gauss-Jordan elimination
+// with partial pivoting: column k is eliminated from every row but the pivot row, so no
+// back substitution (and no further pass of barriers) is needed. The caller pads the system
+// to NP x NP with identity rows and columns and a zero right-hand side there (see
+// lu_solve_rows). Rows stay in their lanes; `pos` tracks the position each row would have
+// after row swaps, so the pivot is the one partial pivoting picks (largest magnitude, ties to
+// the smallest current position). Each step: every wavefront offers its best row (value,
+// position, and the row itself in LDS), one barrier, then every lane takes the best of the W
+// offers and applies the elimination from the LDS copy (broadcast reads). On return every
+// thread of the workgroup can read x from sh.xs (x_c at index c < NP); the return value is 0,
+// or 2 if a pivot was zero. Must be called by all threads of the workgroup.
+template <int NP, int W, typename T>
+__device__ __forceinline__ int gj_solve_mw(T (&a)[NP], T rhs, int row, int lane, int wv,
+                                           GjShared<NP, W, T>& sh) {
+  constexpr int kRow = GjShared<NP, W, T>::kRow;
+  int pos = row;
+  bool singular = false;
+  T mypiv = T(1);
+#pragma unroll
+  for (int k = 0; k < NP; ++k) {
+    const int buf = k & 1;
+    T v = (pos >= k && row < NP) ? absv(a[k]) : T(-1);
+    if (!(v == v)) v = static_cast<T>(__builtin_huge_val());
+    const T vmax = wave_max_pos(v);
+    const uint64_t tied = __ballot(v == vmax);
+    int pl = tied ? __ffsll(static_cast<unsigned long long>(tied)) - 1 : -1;
+    if (pl >= 0 && __popcll(tied) > 1) {
+      int best = bcast(pos, pl);
+      for (uint64_t m = tied & (tied - 1); m; m &= m - 1) {
+        const int l2 = __ffsll(static_cast<unsigned long long>(m)) - 1;
+        const int p2 = bcast(pos, l2);
+        if (p2 < best) { best = p2; pl = l2; }
+      }
+    }
+    if (lane == pl) {
+#pragma unroll
+      for (int j = k & ~3; j < NP; ++j) sh.rows[buf][wv][j] = a[j];
+      sh.rows[buf][wv][NP] = rhs;
+    }
+    const int ppos_w = pl >= 0 ? bcast(pos, pl) : 0x7fffffff;
+    if (lane == 0) {
+      sh.cv[buf][wv] = pl >= 0 ? vmax : T(-1);
+      sh.cp[buf][wv] = ppos_w;
+    }
+    __syncthreads();
+    int ws = 0;
+    T bv = sh.cv[buf][0];
+    int bp = sh.cp[buf][0];
+#pragma unroll
+    for (int w = 1; w < W; ++w) {
+      const T v2 = sh.cv[buf][w];
+      const int p2 = sh.cp[buf][w];
+      const bool take = (v2 > bv) || (v2 == bv && p2 < bp);
+      ws = take ? w : ws;
+      bv = take ? v2 : bv;
+      bp = take ? p2 : bp;
+    }
+    const T* pr = &sh.rows[buf][ws][0];
+    T piv = pr[k];
+    singular |= (piv == T(0));
+    piv = (piv == T(0)) ? T(1) : piv;
+    const bool me = (wv == ws) && (lane == pl);
+    pos = (pos == k) ? bp : pos;
+    pos = me ? k : pos;
+    mypiv = me ? piv : mypiv;
+    const T l = me ? T(0) : a[k] / piv;
+#pragma unroll
+    for (int j0 = k + 1; j0 < kRow; j0 += 8) {
+      T pj[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t)
+        if (j0 + t <= NP) pj[t] = pr[j0 + t];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        if (j0 + t < NP) a[j0 + t] = fma(-l, pj[t], a[j0 + t]);
+        else if (j0 + t == NP) rhs = fma(-l, pj[t], rhs);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  if (row < NP) sh.xs[pos] = rhs / mypiv;
+  __syncthreads();
+  return singular ? 2 : 0;
+}
+
+// Sum of a per-thread double over the workgroup (W wavefronts), two values at once.
+template <int W>
+__device__ __forceinline__ void block_sum2(double& s0, double& s1, int lane, int wv,
+                                           double (&red)[W][2]) {
+  s0 = wave_sum(s0);
+  s1 = wave_sum(s1);
+  if (lane == 0) { red[wv][0] = s0; red[wv][1] = s1; }
+  __syncthreads();
+  s0 = 0.0;
+  s1 = 0.0;
+#pragma unroll
+  for (int w = 0; w < W; ++w) { s0 += red[w][0]; s1 += red[w][1]; }
+}
+
+}  // namespace rb
+
+namespace rb {
+
+// One Newton update of one request whose system is spread over the W wavefronts of the
+// workgroup (NP > 64). Loads J (column-major, leading dimension N) row by row into the lanes,
+// forms the right-hand side -F(u) via rhs_of(row, J_row . u), solves by gj_solve_mw, and
+// adds the correction to the FP64 iterate. Returns the status flag (0 ok, 2 singular,
+// 3 non-finite) and the squared H-norms of the update and of the new iterate. Uniform over
+// the workgroup; every thread must call it.
+template <typename T, int NP, int W, typename RhsOf>
+__device__ __forceinline__ int mw_newton_update(const T* __restrict__ jb, int N, int Nm,
+                                                double* __restrict__ ub,
+                                                const double* __restrict__ H, RhsOf rhs_of,
+                                                GjShared<NP, W, T>& sh, double& nd2,
+                                                double& nu2) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, row = wv * 64 + lane;
+  const int rc = row < N ? row : N - 1;
+  T r[NP];
+  T ju = T(0);
+  bool bad = false;
+#pragma unroll
+  for (int c = 0; c < NP; ++c) {
+    const T v = jb[(c < N ? c : N - 1) * N + rc];
+    r[c] = (c < N && row < N) ? v : (c == row ? T(1) : T(0));
+    ju = fma(r[c], static_cast<T>(ub[c]), ju);
+    bad |= !finite_val(r[c]);
+  }
+  double rhs64 = row < N ? rhs_of(row, ju) : 0.0;
+  const T rhs = static_cast<T>(rhs64);
+  bad |= !finite_val(rhs);
+  int flag = __syncthreads_or(bad) ? 3 : 0;
+  if (flag == 0) flag = gj_solve_mw<NP, W, T>(r, rhs, row, lane, wv, sh);
+  if (flag != 0) return flag;
+  const double dx = row < N ? static_cast<double>(sh.xs[row]) : 0.0;
+  const double un = (row < N ? ub[row] : 0.0) + dx;
+  double hd = dx, hu = un;
+  if (H) {
+    hd = 0.0;
+    hu = 0.0;
+    for (int c = 0; c < N; ++c) {
+      const double h = H[(int64_t)c * Nm + rc];
+      const double xc = static_cast<double>(sh.xs[c]);
+      hd = fma(h, xc, hd);
+      hu = fma(h, ub[c] + xc, hu);
+    }
+  }
+  if (row >= N) { hd = 0.0; hu = 0.0; }
+  nd2 = dx * hd;
+  nu2 = un * hu;
+  __syncthreads();                        // every lane has read ub before it is overwritten
+  block_sum2<W>(nd2, nu2, lane, wv, sh.red);
+  if (!finite_val(nd2) || !finite_val(nu2)) return 3;
+  if (row < N) ub[row] = un;
+  return 0;
+}
+
+}  // namespace rb

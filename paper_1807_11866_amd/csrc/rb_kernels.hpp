@@ -105,7 +105,8 @@ struct NewtonState {
 
 struct NewtonF64Args {
   const double* op;        // packed solve operand
-  int nrb, nks_s, nks;     // row blocks, S-part k-steps, total k-steps (A part at nks_s)
+  int nrb, nks_s, nks;     // row blocks, affine k-steps, total k-steps
+  int nchunk;              // tensor chunks
   int N, Nm, Q, Qc, Qf, B, ldu, maxit;
   double tol;
   const double* ta;        // [B][Q]
@@ -149,31 +150,40 @@ static __global__ void newton_init_kernel(NewtonF64Args a) {
 }
 
 // ------------------------------------------------------------------ contraction ------
-// One MFMA-F64 contraction kernel serves both the Jacobian (+ residual) of a Newton step and
-// the pressure right-hand side. Workgroup g handles the 64-request tile g / kSplit and the
-// row split g % kSplit; with round-robin dispatch over the 8 XCDs every workgroup of one XCD
-// reads the same eighth of the packed operand, which therefore stays in that XCD's L2.
-// Wavefront w of the workgroup owns requests 16w..16w+15 of the tile and keeps its whole
-// slice of W (the B operand, kA + KT k-steps) in registers, so the main loop touches no LDS; the
-// four wavefronts walk the same row blocks in the same order and share each A tile (one
-// 512-byte line per k-step and row block) through L1. Row blocks go four at a time: per
-// k-step four A loads (issued kDepth k-steps ahead; the loop over the tensor k-steps is
-// unrolled at the compile-time length KT, so the pipeline is static) feed four
-// v_mfma_f64_16x16x4f64. The affine k-steps go first and are folded once per row group.
+// One MFMA-F64 contraction kernel serves the Jacobian of a Newton step, the FP64 residual of
+// the mixed-precision refinement and the pressure right-hand side. Workgroup g handles the
+// 64-request tile g / kSplit and the row split g % kSplit; with round-robin dispatch over the
+// 8 XCDs every workgroup of one XCD reads the same eighth of the packed operand, which
+// therefore stays in that XCD's L2. Wavefront w of the workgroup owns requests 16w..16w+15
+// of the tile and keeps its slice of W (the B operand) for one chunk of KC tensor k-steps in
+// registers, so the main loop touches no LDS; the four wavefronts walk the same row blocks
+// in the same order and share each A tile (one 512-byte line per k-step and row block)
+// through L1. Row blocks go four at a time: per k-step four A loads (issued kDepth k-steps
+// ahead; the loop over a chunk is unrolled at the compile-time length KC, so the pipeline is
+// static) feed four v_mfma_f64_16x16x4f64. The affine k-steps go first (chunk 0 only).
+// Tensor parts longer than 64 k-steps run as nchunk chunks; each chunk walks the row blocks
+// again with fresh accumulators, which the residual and pressure epilogues (linear in the
+// accumulator) fold chunk by chunk; for the Jacobian each chunk after the first adds its
+// accumulators to the stored J.
 //
-// Rows are m = j*R + i (R = N for the Jacobian, R = Np for the pressure). The epilogue
-// folds acc[m, b] * u_j(b) into per-row sums p_i(b) in LDS: for the Jacobian right after the
-// affine part of K (giving A(mu) u; with J u this yields F(u) = (J u + A u)/2 - f), for the
-// pressure after all of K (giving A_sv u + C_sv(u,u)). Each workgroup writes its split's
-// partial sums; the solve kernels add the kSplit partials.
+// Rows are m = j*R + i (R = N for the solve operand, R = Np for the pressure one). The
+// epilogue folds acc[m, b] * u_j(b) into per-row sums p_i(b) in LDS:
+//   Jacobian: the affine accumulator (A(mu) u; with J u the LU kernel forms
+//             F(u) = (J u + A u)/2 - f) and stores J;
+//   residual: affine accumulator with weight 1, tensor accumulators with weight 1/2, so
+//             p = A(mu) u + C(mu)(u,u)  (the tensor part applied to u is 2 C(u,u));
+//   pressure: every accumulator with weight 1, p = A_sv u + C_sv(u,u).
+// Each workgroup writes its split's partial sums; the solve kernels add the kSplit partials.
 constexpr int kTile = 64;      // requests per workgroup tile (16 per wavefront)
 constexpr int kSplit = 8;      // row splits, one per XCD
 constexpr int kGroup = 4;      // row blocks per wavefront pass
 constexpr int kDepth = 4;      // k-steps of A operand in flight
+constexpr int kMaxKC = 64;     // longest tensor chunk held in registers
 
 struct ContractArgs {
   const double* op;        // packed operand [nrb][nks][64]
-  int nrb, nks, kA;        // row blocks, k-steps per row block (kA + KT), affine k-steps
+  int nrb, nks, kA;        // row blocks, k-steps per row block (kA + nchunk*KC), affine k-steps
+  int nchunk;              // tensor chunks of KC k-steps
   int R, N, M;             // rows m = j*R + i, M = R*N
   int Q, Qc, B;
   int64_t Bp;              // padded request count (multiple of kTile)
@@ -182,164 +192,170 @@ struct ContractArgs {
   const double* U;         // iterates, row b at U + b*ldU (rows >= B are not read)
   int ldU;
   const int* done;         // Newton flags [Bp] or nullptr
-  double* J;               // Jacobian store [Bp][mp] or nullptr (pressure)
+  double* J;               // Jacobian store [Bp][mp] or nullptr
   int64_t mp;
   double* part;            // partial row sums [kSplit][Bp][ldp]
-  double* part2;           // second partial sums (kModeResid: J u) or nullptr
   int ldp;
 };
 
+// LDS: the tile's iterates [kTile][N] and row sums [kTile][R].
 __host__ __device__ inline int64_t contract_lds_bytes(int N, int R) {
-  return 8 * ((int64_t)kTile * N + 2 * (int64_t)kTile * R + kTile * (kMaxQ + kMaxQc));
+  return 8 * (int64_t)kTile * (N + R);
 }
 
-// kMode: kModeJac (store J, fold A(mu)u), kModePressure (fold A_sv u + C_sv(u,u)),
-// kModeResid (fold A(mu)u into part and J u into part2; nothing stored) -- the FP64 residual
-// F(u) = (J u + A u)/2 - f of the mixed-precision refinement.
 constexpr int kModeJac = 0, kModePressure = 1, kModeResid = 2;
 
-template <int kMode, int KT>
+template <int kMode, int KC>
 __global__ __launch_bounds__(kThreads) void contract_f64_kernel(ContractArgs a) {
-  constexpr bool kJac = kMode != kModePressure;     // affine fold + Newton flags
   extern __shared__ double smem[];
   const int N = a.N, R = a.R;
-  const int kA = a.kA;                     // affine k-steps (1..3); tensor k-steps = KT
+  const int kA = a.kA;                     // affine k-steps (1..3)
   constexpr int kAmax = 3;
   double* ul = smem;                       // [kTile][N]
   double* pl = ul + kTile * N;             // [kTile][R]
-  double* tal = pl + kTile * R;            // [kTile][kMaxQ]
-  double* tcl = tal + kTile * kMaxQ;       // [kTile][kMaxQc]
 
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int split = blockIdx.x % kSplit;
   const int b0 = (blockIdx.x / kSplit) * kTile;
-  if (kJac && a.done && __syncthreads_and(tid < kTile ? a.done[b0 + tid] : 1)) return;
-  double* pl2 = tcl + kTile * kMaxQc;      // [kTile][R] J u (kModeResid only)
+  if (a.done && __syncthreads_and(tid < kTile ? a.done[b0 + tid] : 1)) return;
 
   for (int idx = tid; idx < kTile * N; idx += kThreads) {
     const int b = idx / N, l = idx - b * N, bg = b0 + b;
     ul[idx] = bg < a.B ? a.U[(int64_t)bg * a.ldU + l] : 0.0;
   }
-  for (int idx = tid; idx < kTile * R; idx += kThreads) {
-    pl[idx] = 0.0;
-    if (kMode == kModeResid) pl2[idx] = 0.0;
-  }
-  for (int idx = tid; idx < kTile * kMaxQ; idx += kThreads) {
-    const int b = idx / kMaxQ, q = idx - b * kMaxQ, bg = b0 + b;
-    tal[idx] = (bg < a.B && q < a.Q) ? a.ta[(int64_t)bg * a.Q + q] : 0.0;
-  }
-  for (int idx = tid; idx < kTile * kMaxQc; idx += kThreads) {
-    const int b = idx / kMaxQc, q = idx - b * kMaxQc, bg = b0 + b;
-    tcl[idx] = (bg < a.B && q < a.Qc) ? a.tc[(int64_t)bg * a.Qc + q] : 0.0;
-  }
-  __syncthreads();
+  for (int idx = tid; idx < kTile * R; idx += kThreads) pl[idx] = 0.0;
 
-  // This lane's B-operand column: W[ks*4 + lane/16][b], b = 16*wv + lane%16. Affine part
-  // (rows k < 4*kA: theta^a_k), tensor part (row 4*kA + q*N + l: theta^c_q u_l).
+  // This lane's B-operand column: request bl = 16*wv + lane%16, k = ks*4 + lane/16.
+  // Affine rows k < 4*kA: theta^a_k; tensor row t = q*N + l: theta^c_q u_l.
   const int bl = 16 * wv + (lane & 15);
+  const int bg = b0 + bl;
   const int k0 = lane >> 4;
-  double wA[kAmax], wT[KT];
+  double wA[kAmax], tcv[kMaxQc];
 #pragma unroll
   for (int ks = 0; ks < kAmax; ++ks) {
     const int k = ks * 4 + k0;
-    wA[ks] = (k < kMaxQ) ? tal[bl * kMaxQ + k] : 0.0;
+    wA[ks] = (bg < a.B && k < a.Q) ? a.ta[(int64_t)bg * a.Q + k] : 0.0;
   }
-  {
-    int l = k0, q = 0;
-    while (l >= N && q < kMaxQc) { l -= N; ++q; }
 #pragma unroll
-    for (int ks = 0; ks < KT; ++ks) {
-      wT[ks] = (q < a.Qc) ? tcl[bl * kMaxQc + q] * ul[bl * N + l] : 0.0;
-      l += 4;
-      while (l >= N && q < kMaxQc) { l -= N; ++q; }
-    }
-  }
+  for (int q = 0; q < kMaxQc; ++q) tcv[q] = (bg < a.B && q < a.Qc) ? a.tc[(int64_t)bg * a.Qc + q] : 0.0;
+  __syncthreads();
 
   const int rb_lo = (int)((int64_t)split * a.nrb / kSplit);
   const int rb_hi = (int)((int64_t)(split + 1) * a.nrb / kSplit);
   const int col = bl;                      // accumulator column (request) of this lane
-  const int nks = kA + KT;                 // k-steps per packed row block
+  const int nks = a.nks;
 
-  for (int g0 = rb_lo; g0 < rb_hi; g0 += kGroup) {
-    const double* opg[kGroup];
+  // Accumulator layout of v_mfma_f64_16x16x4f64: lane l, element v = row l/16 + 4v,
+  // column l%16 of the 16x16 tile. fold(): w * acc[m] * u_j into p_i for m = j*R + i.
+  auto fold = [&](const f64x4 (&c)[kGroup], int g0, double w) {
+    const int m0 = g0 * 16 + (lane >> 4);
+    const int j0 = m0 / R, i0 = m0 - j0 * R;
 #pragma unroll
-    for (int r = 0; r < kGroup; ++r)
-      opg[r] = a.op + (int64_t)min(g0 + r, rb_hi - 1) * nks * 64 + lane;
-    double xa[kAmax][kGroup];
+    for (int r = 0; r < kGroup; ++r) {
+      if (g0 + r < rb_hi) {
 #pragma unroll
-    for (int ks = 0; ks < kAmax; ++ks)
-#pragma unroll
-      for (int r = 0; r < kGroup; ++r) xa[ks][r] = opg[r][min(ks, kA - 1) * 64];
-    double x[KT][kGroup];
-#pragma unroll
-    for (int ks = 0; ks < kDepth && ks < KT; ++ks)
-#pragma unroll
-      for (int r = 0; r < kGroup; ++r) x[ks][r] = opg[r][(kA + ks) * 64];
-
-    f64x4 c[kGroup];
-#pragma unroll
-    for (int r = 0; r < kGroup; ++r) c[r] = f64x4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int ks = 0; ks < kAmax; ++ks) {
-      if (ks < kA) {
-#pragma unroll
-        for (int r = 0; r < kGroup; ++r)
-          c[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[ks][r], wA[ks], c[r], 0, 0, 0);
-      }
-    }
-
-    // Accumulator layout of v_mfma_f64_16x16x4f64: lane l, element v = row l/16 + 4v,
-    // column l%16 of the 16x16 tile. fold(): acc[m] * u_j into p_i for m = j*R + i.
-    auto fold = [&](double* dst) {
-      const int m0 = g0 * 16 + (lane >> 4);
-      const int j0 = m0 / R, i0 = m0 - j0 * R;
-#pragma unroll
-      for (int r = 0; r < kGroup; ++r) {
-        if (g0 + r < rb_hi) {
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            int i = i0 + 16 * r + 4 * v, j = j0;
-            while (i >= R) { i -= R; ++j; }
-            if (j < N) atomicAdd(&dst[col * R + i], c[r][v] * ul[col * N + j]);
-          }
+        for (int v = 0; v < 4; ++v) {
+          int i = i0 + 16 * r + 4 * v, j = j0;
+          while (i >= R) { i -= R; ++j; }
+          if (j < N) atomicAdd(&pl[col * R + i], w * c[r][v] * ul[col * N + j]);
         }
       }
-    };
-    if (kJac) fold(pl);                    // affine part done: A(mu) u
+    }
+  };
 
+  for (int ch = 0; ch < a.nchunk; ++ch) {
+    double wT[KC];
+    {
+      int t = ch * KC * 4 + k0, q = 0;
+      while (t >= N && q < kMaxQc) { t -= N; ++q; }
+      if (q >= kMaxQc) t = 0;              // padding k-steps: W = 0, any valid index
 #pragma unroll
-    for (int ks = 0; ks < KT; ++ks) {
-      if (ks + kDepth < KT) {
+      for (int ks = 0; ks < KC; ++ks) {
+        double tq = 0.0;
 #pragma unroll
-        for (int r = 0; r < kGroup; ++r) x[ks + kDepth][r] = opg[r][(kA + ks + kDepth) * 64];
+        for (int qq = 0; qq < kMaxQc; ++qq) tq = (q == qq) ? tcv[qq] : tq;
+        wT[ks] = tq * ul[bl * N + t];
+        t += 4;
+        while (t >= N && q < kMaxQc) { t -= N; ++q; }
+        if (q >= kMaxQc) t = 0;
       }
+    }
+    const int kt0 = kA + ch * KC;          // first k-step of this chunk
+
+    for (int g0 = rb_lo; g0 < rb_hi; g0 += kGroup) {
+      const double* opg[kGroup];
 #pragma unroll
       for (int r = 0; r < kGroup; ++r)
-        c[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[ks][r], wT[ks], c[r], 0, 0, 0);
-    }
-
-    if (kMode == kModeJac) {
+        opg[r] = a.op + (int64_t)min(g0 + r, rb_hi - 1) * nks * 64 + lane;
+      double x[KC][kGroup];
 #pragma unroll
-      for (int r = 0; r < kGroup; ++r) {
-        if (g0 + r < rb_hi) {
-          double* jp = a.J + (int64_t)(b0 + col) * a.mp + (g0 + r) * 16 + (lane >> 4);
-          jp[0] = c[r][0];
-          jp[4] = c[r][1];
-          jp[8] = c[r][2];
-          jp[12] = c[r][3];
+      for (int ks = 0; ks < kDepth && ks < KC; ++ks)
+#pragma unroll
+        for (int r = 0; r < kGroup; ++r) x[ks][r] = opg[r][(kt0 + ks) * 64];
+
+      f64x4 c[kGroup];
+#pragma unroll
+      for (int r = 0; r < kGroup; ++r) c[r] = f64x4{0.0, 0.0, 0.0, 0.0};
+      if (ch == 0) {
+        double xa[kAmax][kGroup];
+#pragma unroll
+        for (int ks = 0; ks < kAmax; ++ks)
+#pragma unroll
+          for (int r = 0; r < kGroup; ++r) xa[ks][r] = opg[r][min(ks, kA - 1) * 64];
+#pragma unroll
+        for (int ks = 0; ks < kAmax; ++ks) {
+          if (ks < kA) {
+#pragma unroll
+            for (int r = 0; r < kGroup; ++r)
+              c[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[ks][r], wA[ks], c[r], 0, 0, 0);
+          }
+        }
+        if (kMode != kModePressure) fold(c, g0, 1.0);     // A(mu) u
+        if (kMode == kModeResid) {
+#pragma unroll
+          for (int r = 0; r < kGroup; ++r) c[r] = f64x4{0.0, 0.0, 0.0, 0.0};
         }
       }
-    } else if (kMode == kModeResid) {
-      fold(pl2);                           // J u
-    } else {
-      fold(pl);                            // A_sv u + C_sv(u,u)
+
+#pragma unroll
+      for (int ks = 0; ks < KC; ++ks) {
+        if (ks + kDepth < KC) {
+#pragma unroll
+          for (int r = 0; r < kGroup; ++r) x[ks + kDepth][r] = opg[r][(kt0 + ks + kDepth) * 64];
+        }
+#pragma unroll
+        for (int r = 0; r < kGroup; ++r)
+          c[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[ks][r], wT[ks], c[r], 0, 0, 0);
+      }
+
+      if (kMode == kModeJac) {
+        // chunks after the first add to what the same lane stored before
+#pragma unroll
+        for (int r = 0; r < kGroup; ++r) {
+          if (g0 + r < rb_hi) {
+            double* jp = a.J + (int64_t)(b0 + col) * a.mp + (g0 + r) * 16 + (lane >> 4);
+            if (ch == 0) {
+              jp[0] = c[r][0];
+              jp[4] = c[r][1];
+              jp[8] = c[r][2];
+              jp[12] = c[r][3];
+            } else {
+              jp[0] += c[r][0];
+              jp[4] += c[r][1];
+              jp[8] += c[r][2];
+              jp[12] += c[r][3];
+            }
+          }
+        }
+      } else {
+        fold(c, g0, kMode == kModeResid ? 0.5 : 1.0);
+      }
     }
   }
   __syncthreads();
   for (int idx = tid; idx < kTile * R; idx += kThreads) {
     const int b = idx / R, i = idx - b * R;
     a.part[((int64_t)split * a.Bp + b0 + b) * a.ldp + i] = pl[idx];
-    if (kMode == kModeResid) a.part2[((int64_t)split * a.Bp + b0 + b) * a.ldp + i] = pl2[idx];
   }
 }
 
@@ -405,6 +421,36 @@ __global__ __launch_bounds__(kThreads) void lu_f64_kernel(NewtonF64Args a, int i
   }
   if (flag != 0 && lane == 0) {
     a.s.status[b] = flag;
+    a.s.done[b] = 1;
+  }
+}
+
+// NP > 64: one request per workgroup of W wavefronts (Gauss-Jordan over the workgroup).
+template <int NP, int W>
+__global__ __launch_bounds__(kWave * W) void lu_f64_mw_kernel(NewtonF64Args a, int it) {
+  __shared__ GjShared<NP, W, double> sh;
+  const int b = blockIdx.x;
+  if (a.s.done[b]) return;
+  const int N = a.N;
+  const double* jb = a.s.J + (int64_t)b * a.s.mp;
+  double* ub = a.s.U + (int64_t)b * NP;
+  auto rhs_of = [&](int row, double ju) {
+    double w = 0.0;
+#pragma unroll
+    for (int sp = 0; sp < kSplit; ++sp) w += a.s.Wv[((int64_t)sp * a.s.Bp + b) * NP + row];
+    return -(0.5 * (ju + w) - a.s.Fv[(int64_t)b * NP + row]);
+  };
+  double nd2, nu2;
+  const int flag = mw_newton_update<double, NP, W>(jb, N, a.Nm, ub, a.H, rhs_of, sh, nd2, nu2);
+  if (threadIdx.x != 0) return;
+  if (flag != 0) {
+    a.s.status[b] = flag;
+    a.s.done[b] = 1;
+    return;
+  }
+  a.s.iters[b] = it + 1;
+  if (sqrt(nd2) <= a.tol * sqrt(nu2)) {
+    a.s.status[b] = 0;
     a.s.done[b] = 1;
   }
 }

@@ -11,11 +11,25 @@
 namespace rb {
 namespace launch {
 
+// FP64 contraction (chunk length (g.nks - g.kA) / g.nchunk: even, <= 64).
 int contract_f64(int mode, const ContractArgs& g, hipStream_t st);
+// FP64 Newton LU: NP <= 64 one wavefront per system, NP > 64 (multiple of 8, <= 96) one
+// workgroup per system.
 int lu_f64(int NP, const NewtonF64Args& a, int it, bool lds_bcast, hipStream_t st);
 int plu_f64(int NPP, const PressureF64Args& a, bool lds_bcast, hipStream_t st);
+// Low-precision contraction: BF16 KT <= 20; FP32 KT even <= 64 or a multiple of 4 <= 152.
 int contract_lp(bool bf16, int KT, const ContractLpArgs& g, hipStream_t st);
+// FP32 LU of the mixed-precision Newton: NP <= 64 or a multiple of 8 <= 152.
 int lu_lp(int NP, bool refine, const LpNewtonArgs& a, int it, hipStream_t st);
+
+// per-TU pieces behind the dispatchers above
+int contract_f64_jac(const ContractArgs& g, hipStream_t st);
+int contract_f64_press(const ContractArgs& g, hipStream_t st);
+int contract_f64_resid(const ContractArgs& g, hipStream_t st);
+int lu_f64_mw(int NP, const NewtonF64Args& a, int it, hipStream_t st);
+int lu_lp_mw(int NP, bool refine, const LpNewtonArgs& a, int it, hipStream_t st);
+int lu_lp_mw_wide(int NP, bool refine, const LpNewtonArgs& a, int it, hipStream_t st);
+int contract_lp_f32_wide(int KT, const ContractLpArgs& g, hipStream_t st);
 
 }  // namespace launch
 }  // namespace rb

@@ -1,4 +1,4 @@
-// Instantiations of contract_f64_kernel<kModePressure, KT> for every even tensor length KT <= 64.
+// Instantiations of contract_f64_kernel<kModePressure, KT> for every even tensor chunk length KC <= 64.
 #include "rb_launch.hpp"
 
 namespace rb {
@@ -17,7 +17,8 @@ static int go(const ContractArgs& g, hipStream_t st) {
 }
 
 int contract_f64_press(const ContractArgs& g, hipStream_t st) {
-  switch (g.nks - g.kA) {
+  if (g.nchunk < 1 || (g.nks - g.kA) % g.nchunk) return -5;
+  switch ((g.nks - g.kA) / g.nchunk) {
 #define RB_KT(n) case n: return go<n>(g, st);
     RB_KT(2) RB_KT(4) RB_KT(6) RB_KT(8) RB_KT(10) RB_KT(12) RB_KT(14) RB_KT(16) RB_KT(18)
     RB_KT(20) RB_KT(22) RB_KT(24) RB_KT(26) RB_KT(28) RB_KT(30) RB_KT(32) RB_KT(34) RB_KT(36)

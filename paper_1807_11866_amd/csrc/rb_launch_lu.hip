@@ -5,10 +5,6 @@
 namespace rb {
 namespace launch {
 
-int contract_f64_jac(const ContractArgs& g, hipStream_t st);
-int contract_f64_press(const ContractArgs& g, hipStream_t st);
-int contract_f64_resid(const ContractArgs& g, hipStream_t st);
-
 int contract_f64(int mode, const ContractArgs& g, hipStream_t st) {
   if (mode == kModeJac) return contract_f64_jac(g, st);
   if (mode == kModePressure) return contract_f64_press(g, st);
@@ -39,6 +35,7 @@ static int go_plu(const PressureF64Args& a, bool lds, hipStream_t st) {
   X(52) X(56) X(60) X(64)
 
 int lu_f64(int NP, const NewtonF64Args& a, int it, bool lds, hipStream_t st) {
+  if (NP > 64) return lu_f64_mw(NP, a, it, st);
   switch (NP) {
 #define RB_C(n) case n: return go_lu<n>(a, it, lds, st);
     RB_NP_CASES(RB_C)

@@ -97,13 +97,14 @@ struct ContractLpArgs {
 };
 
 __host__ __device__ inline int64_t contract_lp_lds_bytes(int N) {
-  return 4 * (2 * (int64_t)kTile * N + kTile * (kMaxQ + kMaxQc));
+  return 4 * 2 * (int64_t)kTile * N;
 }
 
 // Same decomposition as contract_f64_kernel (64-request tile x row split per workgroup,
 // 16 requests and their W slice per wavefront, four row blocks per pass, static prefetch),
-// with FP32 (or BF16) operands and FP32 accumulators. Accumulator layout of the 16x16 FP32
-// MFMAs: lane l, element v = row 4*(l/16) + v, column l%16.
+// with FP32 (or BF16) operands and FP32 accumulators; the whole tensor part (KT k-steps) is
+// one chunk. Accumulator layout of the 16x16 FP32 MFMAs: lane l, element v = row
+// 4*(l/16) + v, column l%16.
 template <bool kBF16, int KT>
 __global__ __launch_bounds__(kThreads) void contract_lp_kernel(ContractLpArgs a) {
   extern __shared__ float smemf[];
@@ -113,8 +114,6 @@ __global__ __launch_bounds__(kThreads) void contract_lp_kernel(ContractLpArgs a)
   const int N = a.N;
   float* ul = smemf;                       // [kTile][N]
   float* pl = ul + kTile * N;              // [kTile][N]
-  float* tal = pl + kTile * N;             // [kTile][kMaxQ]
-  float* tcl = tal + kTile * kMaxQ;        // [kTile][kMaxQc]
 
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int split = blockIdx.x % kSplit;
@@ -126,23 +125,31 @@ __global__ __launch_bounds__(kThreads) void contract_lp_kernel(ContractLpArgs a)
     ul[idx] = bg < a.B ? static_cast<float>(a.U[(int64_t)bg * a.ldU + l]) : 0.f;
     pl[idx] = 0.f;
   }
-  for (int idx = tid; idx < kTile * kMaxQ; idx += kThreads) {
-    const int b = idx / kMaxQ, q = idx - b * kMaxQ, bg = b0 + b;
-    tal[idx] = (bg < a.B && q < a.Q) ? static_cast<float>(a.ta[(int64_t)bg * a.Q + q]) : 0.f;
-  }
-  for (int idx = tid; idx < kTile * kMaxQc; idx += kThreads) {
-    const int b = idx / kMaxQc, q = idx - b * kMaxQc, bg = b0 + b;
-    tcl[idx] = (bg < a.B && q < a.Qc) ? static_cast<float>(a.tc[(int64_t)bg * a.Qc + q]) : 0.f;
-  }
-  __syncthreads();
-
   // W column of this lane: request bl, k = ks*kK + (kBF16 ? 8*(lane/16) + t : lane/16).
   const int bl = 16 * wv + (lane & 15);
+  const int bg = b0 + bl;
+  float tav[kMaxQ], tcv[kMaxQc];
+#pragma unroll
+  for (int q = 0; q < kMaxQ; ++q)
+    tav[q] = (bg < a.B && q < a.Q) ? static_cast<float>(a.ta[(int64_t)bg * a.Q + q]) : 0.f;
+#pragma unroll
+  for (int q = 0; q < kMaxQc; ++q)
+    tcv[q] = (bg < a.B && q < a.Qc) ? static_cast<float>(a.tc[(int64_t)bg * a.Qc + q]) : 0.f;
+  __syncthreads();
+
   auto wval = [&](int k) -> float {
-    if (k < kK * a.kA) return k < kMaxQ ? tal[bl * kMaxQ + k] : 0.f;
+    if (k < kK * a.kA) {
+      float v = 0.f;
+#pragma unroll
+      for (int q = 0; q < kMaxQ; ++q) v = (k == q) ? tav[q] : v;
+      return v;
+    }
     int l = k - kK * a.kA, q = 0;
     while (l >= N && q < kMaxQc) { l -= N; ++q; }
-    return q < a.Qc ? tcl[bl * kMaxQc + q] * ul[bl * N + l] : 0.f;
+    float tq = 0.f;
+#pragma unroll
+    for (int qq = 0; qq < kMaxQc; ++qq) tq = (q == qq) ? tcv[qq] : tq;
+    return q < kMaxQc ? tq * ul[bl * N + l] : 0.f;
   };
   opnd wA[kAmax], wT[KT];
   auto make = [&](int ks) -> opnd {
@@ -245,17 +252,16 @@ struct LpNewtonArgs {
   const double* H;         // [Nm][Nm] norm Gram or nullptr
   const float* J;          // [Bp][mp]
   int64_t mp;
-  const float* part;       // [kSplit][Bp][NP] A(mu) u (FP32 iteration)
-  const double* partA;     // [kSplit][Bp][NP] A(mu) u (FP64 refinement)
-  const double* partJ;     // [kSplit][Bp][NP] J(u) u (FP64 refinement)
+  const float* part;       // [kSplit][Bp][NP] A(mu) u (low-precision phase)
+  const double* partA;     // [kSplit][Bp][NP] A(mu) u + C(mu)(u,u) (FP64 refinement)
   NewtonState s;           // FP64 iterates, f, flags
 };
 
 // One wavefront per request. Low-precision phase (kRefine = false): F(u) ~ (J u + A u)/2 - f
 // from the FP32 / BF16 contraction, a request stops when its update is below tol or has
 // stagnated (below stag and no longer halving). Refinement (kRefine = true): F(u) =
-// (J u + A u)/2 - f from the FP64 contraction with the Jacobian of the last low-precision
-// step. Either way the correction solves J32 delta = -F(u) by the FP32 register LU and is
+// A(mu)u + C(mu)(u,u) - f from the FP64 residual contraction, with the Jacobian of the last
+// low-precision step. Either way the correction solves J32 delta = -F(u) by the FP32 register LU and is
 // added to the FP64 iterate.
 template <int NP, bool kRefine>
 __global__ __launch_bounds__(kThreads) void lu_lp_kernel(LpNewtonArgs a, int it) {
@@ -281,13 +287,10 @@ __global__ __launch_bounds__(kThreads) void lu_lp_kernel(LpNewtonArgs a, int it)
   }
   if (lane < N) {
     if (kRefine) {
-      double au = 0.0, jv = 0.0;
+      double g = 0.0;
 #pragma unroll
-      for (int sp = 0; sp < kSplit; ++sp) {
-        au += a.partA[((int64_t)sp * Bp + b) * NP + lane];
-        jv += a.partJ[((int64_t)sp * Bp + b) * NP + lane];
-      }
-      rhs64 = -(0.5 * (jv + au) - a.s.Fv[(int64_t)b * NP + lane]);
+      for (int sp = 0; sp < kSplit; ++sp) g += a.partA[((int64_t)sp * Bp + b) * NP + lane];
+      rhs64 = -(g - a.s.Fv[(int64_t)b * NP + lane]);
     } else {
       float au = 0.f;
 #pragma unroll
@@ -335,6 +338,48 @@ __global__ __launch_bounds__(kThreads) void lu_lp_kernel(LpNewtonArgs a, int it)
     a.s.status[b] = flag;
     a.s.done[b] = 1;
   }
+}
+
+// NP > 64: one request per workgroup of W wavefronts (Gauss-Jordan over the workgroup),
+// same right-hand sides and stopping rules as lu_lp_kernel.
+template <int NP, int W>
+__global__ __launch_bounds__(kWave * W) void lu_lp_mw_kernel(LpNewtonArgs a, int it, int refine) {
+  __shared__ GjShared<NP, W, float> sh;
+  const int b = blockIdx.x;
+  if (a.s.done[b]) return;
+  const int64_t Bp = a.s.Bp;
+  const float* jb = a.J + (int64_t)b * a.mp;
+  double* ub = a.s.U + (int64_t)b * NP;
+  auto rhs_of = [&](int row, float ju) {
+    const double f = a.s.Fv[(int64_t)b * NP + row];
+    if (refine) {
+      double g = 0.0;
+#pragma unroll
+      for (int sp = 0; sp < kSplit; ++sp) g += a.partA[((int64_t)sp * Bp + b) * NP + row];
+      return -(g - f);
+    }
+    float au = 0.f;
+#pragma unroll
+    for (int sp = 0; sp < kSplit; ++sp) au += a.part[((int64_t)sp * Bp + b) * NP + row];
+    return -(0.5 * (static_cast<double>(ju) + au) - f);
+  };
+  double nd2, nu2;
+  const int flag = mw_newton_update<float, NP, W>(jb, a.N, a.Nm, ub, a.H, rhs_of, sh, nd2, nu2);
+  if (threadIdx.x != 0) return;
+  if (flag != 0) {
+    a.s.status[b] = flag;
+    a.s.done[b] = 1;
+    return;
+  }
+  a.s.iters[b] = a.s.iters[b] + 1;
+  const double nd = sqrt(nd2), nu = sqrt(nu2);
+  if (nd <= a.tol * nu) {
+    a.s.status[b] = 0;
+    a.s.done[b] = 1;
+  } else if (!refine && it > 0 && nd <= a.stag * nu && nd > 0.5 * a.s.dprev[b]) {
+    a.s.done[b] = 1;
+  }
+  if (!refine) a.s.dprev[b] = nd;
 }
 
 // Between the phases: every request without a failure status is refined (status back to

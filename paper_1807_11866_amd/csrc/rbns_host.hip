@@ -47,6 +47,7 @@ struct DevBuf {
 struct Pack {              // packed MFMA operand for one basis size
   DevBuf buf;
   int nrb = 0, nks_s = 0, nks = 0;
+  int nchunk = 1;          // tensor part = nchunk chunks of (nks - nks_s) / nchunk k-steps
 };
 
 struct Set {
@@ -129,17 +130,27 @@ int launch_grid(int64_t total) {
   return (int)(g > 65536 ? 65536 : (g < 1 ? 1 : g));
 }
 
-// Solve operand for basis size N (built once on the device, then cached).
-// k-steps of a packed row block: affine part ceil(Q/4), tensor part ceil(Qc*N/4) rounded up
-// to even (the contraction kernel is instantiated per even tensor length).
+// k-steps of a packed row block: affine part ceil(Q/4), tensor part ceil(Qc*N/4) split into
+// nchunk <= 64-k-step chunks of an even length KC (the FP64 contraction is instantiated per
+// even chunk length and holds one chunk of W in registers), zero padded.
 int affine_ksteps(int Q) { return (Q + 3) / 4; }
-int tensor_ksteps(int Qc, int N) { return (int)ceil_to(ceil_to((int64_t)Qc * N, 4) / 4, 2); }
-int total_ksteps(int Q, int Qc, int N) { return affine_ksteps(Q) + tensor_ksteps(Qc, N); }
+void tensor_chunks(int Qc, int N, int* nchunk, int* kc) {
+  const int raw = (int)(ceil_to((int64_t)Qc * N, 4) / 4);
+  *nchunk = (raw + rb::kMaxKC - 1) / rb::kMaxKC;
+  *kc = (int)ceil_to((raw + *nchunk - 1) / *nchunk, 2);
+}
+int tensor_ksteps(int Qc, int N) {
+  int n, kc;
+  tensor_chunks(Qc, N, &n, &kc);
+  return n * kc;
+}
 
 int make_pack(rb_ctx* c, Set* s, int N, int R, bool solve, Pack* p) {
   p->nrb = (int)(ceil_to((int64_t)N * R, 16) / 16);
   p->nks_s = affine_ksteps(s->Q);
-  p->nks = total_ksteps(s->Q, s->Qc, N);
+  int kc;
+  tensor_chunks(s->Qc, N, &p->nchunk, &kc);
+  p->nks = p->nks_s + p->nchunk * kc;
   const int64_t total = (int64_t)p->nrb * p->nks * 64;
   int rc = dev_alloc(c, p->buf, total * sizeof(double));
   if (rc) return rc;
@@ -177,8 +188,12 @@ int press_pack_f64(rb_ctx* c, Set* s, int N, int Np, Pack** out) {
 }
 
 // Mixed-precision packed operand for basis size N (FP32 or BF16 copy of the FP64 tensors).
+// FP32: ceil(Qc*N/4) k-steps rounded up to even (to a multiple of 4 beyond 64); BF16:
+// ceil(Qc*N/32) k-steps of 32. The whole tensor part is held in registers.
 int lp_tensor_ksteps(int Qc, int N, bool bf16) {
-  return bf16 ? (int)(ceil_to((int64_t)Qc * N, 32) / 32) : tensor_ksteps(Qc, N);
+  if (bf16) return (int)(ceil_to((int64_t)Qc * N, 32) / 32);
+  const int raw = (int)(ceil_to((int64_t)Qc * N, 4) / 4);
+  return (int)ceil_to(raw, raw > 64 ? 4 : 2);
 }
 
 int solve_pack_lp(rb_ctx* c, Set* s, int N, bool bf16, Pack** out) {
@@ -256,7 +271,9 @@ rb::NewtonState carve_state(void* base, int64_t Bp, int NP, int64_t mp) {
   return s;
 }
 
-int np_bucket(int n) { return (int)ceil_to(n, 4); }
+// Register row length of the LU kernels: multiples of 4 up to 64 (one wavefront per system),
+// multiples of 8 beyond (one workgroup of ceil(NP/64) wavefronts per system).
+int np_bucket(int n) { return (int)ceil_to(n, n <= 64 ? 4 : 8); }
 
 enum { FAM_JACOBIAN = 0, FAM_LU = 1, FAM_PRESSURE = 2, FAM_RESIDUAL = 3, FAM_COUNT = 4 };
 const char* const kFamilies[FAM_COUNT] = {"jacobian", "lu", "pressure", "residual"};
@@ -300,14 +317,14 @@ int enqueue_newton(rb_ctx* c, const rb::NewtonF64Args& a, hipStream_t st) {
   const int64_t Bp = a.s.Bp;
   rb::ContractArgs g;
   g.op = a.op;
-  g.nrb = a.nrb; g.nks = a.nks; g.kA = a.nks_s;
+  g.nrb = a.nrb; g.nks = a.nks; g.kA = a.nks_s; g.nchunk = a.nchunk;
   g.R = a.N; g.N = a.N; g.M = a.N * a.N;
   g.Q = a.Q; g.Qc = a.Qc; g.B = a.B; g.Bp = Bp;
   g.ta = a.ta; g.tc = a.tc;
   g.U = a.s.U; g.ldU = NP;
   g.done = a.s.done;
   g.J = a.s.J; g.mp = a.s.mp;
-  g.part = a.s.Wv; g.part2 = nullptr; g.ldp = NP;
+  g.part = a.s.Wv; g.ldp = NP;
   hipLaunchKernelGGL(rb::newton_init_kernel, dim3(launch_grid(Bp * NP)), dim3(256), 0, st, a);
   for (int it = 0; it < a.maxit; ++it) {
     {
@@ -340,7 +357,6 @@ int enqueue_newton_lp(rb_ctx* c, Set* s, const rb::NewtonF64Args& a, bool bf16, 
   float* part32 = J32 + Bp * mp;
   double* partA = (double*)(part32 + rb::kSplit * Bp * NP + 64);
   partA = (double*)(((uintptr_t)partA + 255) & ~(uintptr_t)255);
-  double* partJ = partA + rb::kSplit * Bp * NP;
 
   rb::ContractLpArgs gl;
   gl.op = pl->buf.p;
@@ -354,18 +370,18 @@ int enqueue_newton_lp(rb_ctx* c, Set* s, const rb::NewtonF64Args& a, bool bf16, 
 
   rb::ContractArgs gr;                      // FP64 residual
   gr.op = (const double*)pf->buf.p;
-  gr.nrb = pf->nrb; gr.nks = pf->nks; gr.kA = pf->nks_s;
+  gr.nrb = pf->nrb; gr.nks = pf->nks; gr.kA = pf->nks_s; gr.nchunk = pf->nchunk;
   gr.R = N; gr.N = N; gr.M = N * N;
   gr.Q = a.Q; gr.Qc = a.Qc; gr.B = a.B; gr.Bp = Bp;
   gr.ta = a.ta; gr.tc = a.tc; gr.U = a.s.U; gr.ldU = NP;
   gr.done = a.s.done; gr.J = nullptr; gr.mp = 0;
-  gr.part = partA; gr.part2 = partJ; gr.ldp = NP;
+  gr.part = partA; gr.ldp = NP;
 
   rb::LpNewtonArgs la;
   la.N = N; la.Nm = a.Nm; la.B = a.B;
   la.tol = a.tol; la.H = a.H;
   la.stag = bf16 ? 5e-2 : 1e-3;
-  la.J = J32; la.mp = mp; la.part = part32; la.partA = partA; la.partJ = partJ;
+  la.J = J32; la.mp = mp; la.part = part32; la.partA = partA;
   la.s = a.s;
 
   hipLaunchKernelGGL(rb::newton_init_kernel, dim3(launch_grid(Bp * NP)), dim3(256), 0, st, a);
@@ -397,7 +413,7 @@ int enqueue_newton_lp(rb_ctx* c, Set* s, const rb::NewtonF64Args& a, bool bf16, 
 
 size_t lp_extra_bytes(int64_t Bp, int NP, int64_t mp) {
   return (size_t)(Bp * mp + rb::kSplit * Bp * NP + 64) * sizeof(float) + 512 +
-         (size_t)2 * rb::kSplit * Bp * NP * sizeof(double);
+         (size_t)rb::kSplit * Bp * NP * sizeof(double);
 }
 
 }  // namespace
@@ -534,6 +550,9 @@ int rb_solve_batch(rb_ctx* c, int set, int B, int N, int ldu, const double* ta,
     return fail(RB_E_INVAL, "rb_solve_batch: unknown precision %d", o.precision);
   if (o.precision != RB_PREC_F64 && (o.refine_steps < 0 || o.refine_steps > 100))
     return fail(RB_E_INVAL, "rb_solve_batch: refine_steps=%d", o.refine_steps);
+  if (o.precision == RB_PREC_F64 && N > RB_MAX_N_F64)
+    return fail(RB_E_UNSUPPORTED, "rb_solve_batch: FP64 solves take N <= %d (N=%d)",
+                RB_MAX_N_F64, N);
   if (B == 0) return RB_OK;
   if (!ta || !tc || (!tf && !fover) || !u || !iters || !status)
     return fail(RB_E_INVAL, "rb_solve_batch: NULL array");
@@ -550,7 +569,7 @@ int rb_solve_batch(rb_ctx* c, int set, int B, int N, int ldu, const double* ta,
   if (int rc = workspace(c, stream, ws, &w)) return rc;
   rb::NewtonF64Args a;
   a.op = (const double*)pk->buf.p;
-  a.nrb = pk->nrb; a.nks_s = pk->nks_s; a.nks = pk->nks;
+  a.nrb = pk->nrb; a.nks_s = pk->nks_s; a.nks = pk->nks; a.nchunk = pk->nchunk;
   a.N = N; a.Nm = s->N; a.Q = s->Q; a.Qc = s->Qc; a.Qf = s->Qf; a.B = B; a.ldu = ldu;
   a.maxit = o.max_iter; a.tol = o.tol;
   a.ta = ta; a.tc = tc; a.tf = tf; a.fover = fover; a.u0 = u0;
@@ -597,14 +616,14 @@ int rb_recover_pressure(rb_ctx* c, int set, int B, int N, int Np, int ldu, int l
   hipStream_t st = (hipStream_t)stream;
   rb::ContractArgs g;
   g.op = (const double*)pk->buf.p;
-  g.nrb = pk->nrb; g.nks = pk->nks; g.kA = pk->nks_s;
+  g.nrb = pk->nrb; g.nks = pk->nks; g.kA = pk->nks_s; g.nchunk = pk->nchunk;
   g.R = Np; g.N = N; g.M = Np * N;
   g.Q = s->Q; g.Qc = s->Qc; g.B = B; g.Bp = Bp;
   g.ta = ta; g.tc = tc;
   g.U = u; g.ldU = ldu;
   g.done = nullptr;
   g.J = nullptr; g.mp = 0;
-  g.part = (double*)w->buf.p; g.part2 = nullptr; g.ldp = NPP;
+  g.part = (double*)w->buf.p; g.ldp = NPP;
   rb::PressureF64Args a;
   a.Np = Np; a.Npm = s->Np; a.Qf = s->Qf; a.Qb = s->Qb; a.B = B; a.ldp = ldp; a.Bp = Bp;
   a.tf = tf; a.tb = tb;

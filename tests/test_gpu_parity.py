@@ -45,6 +45,8 @@ def _dev(x, dtype=torch.float64):
 
 
 def _random_set(N, Q=3, Qc=2, Qf=2, Np=5, Qb=2, seed=0, scale=0.05, H=True):
+    """Random SPD A_q, C_q skew in (i, k) (so c(u, v, v) = 0 as for solenoidal fields), a
+    pressure block near the identity; scale keeps Newton from u = 0 convergent."""
     rng = np.random.default_rng(seed)
     A = rng.standard_normal((Q, N, N))
     A = np.einsum("qij,qkj->qik", A, A) / N + 2 * np.eye(N)[None]
@@ -294,6 +296,72 @@ def test_mixed_status_codes(R, c1):
         g = _mixed(R, s, th, prec, 2)
         assert list(g["status"][1:]) == [2, 3], prec
         assert list(g["iters"][1:]) == [0, 0], prec
+    s.close()
+
+
+# ------------------------------------------------------------- large bases ---------
+# N > 64: one workgroup of ceil(N/64) wavefronts per system (Gauss-Jordan LU), contraction
+# tensor parts longer than 64 k-steps in chunks.
+
+@pytest.mark.parametrize("N", [72, 96])
+def test_fp64_large_n_random(O, R, N):
+    ts = _random_set(N, Qc=4, seed=200 + N)     # Qc*N/4 > 64: chunked Jacobian
+    mu = np.column_stack([np.linspace(0.0, 0.6, 21), np.linspace(100, 1000, 21)])
+    s = R.Solver(ts)
+    th, g = _gpu_solve(R, s, ts, mu, max_iter=20)
+    r = O.solve_batch(O.OracleSet(ts), mu, maxit=20, pressure_np=ts.Np)
+    assert np.array_equal(g["status"], r["status"]) and np.all(g["status"] == 0)
+    assert np.max(_rel(g["u"], r["u"])) <= TOL_F64
+    p = s.pressure(th, torch.as_tensor(g["u"]).cuda())
+    torch.cuda.synchronize()
+    assert np.max(_rel(p["p"].cpu().numpy(), r["p"])) <= TOL_F64
+    s.close()
+
+
+@pytest.mark.parametrize("N", [65, 100, 130, 152])
+def test_mixed_large_n_random(O, R, N):
+    ts = _random_set(N, Qc=4, seed=300 + N)
+    mu = np.column_stack([np.linspace(0.0, 0.6, 21), np.linspace(100, 1000, 21)])
+    s = R.Solver(ts)
+    th = s.theta(_dev(mu))
+    r = O.solve_batch(O.OracleSet(ts), mu, maxit=20)
+    for prec, refine in (("F32", 2), ("BF16", 6)):
+        g = _mixed(R, s, th, prec, refine, max_iter=20)
+        assert np.all(g["status"] <= 1), prec
+        assert np.max(_rel(g["u"], r["u"])) <= TOL_MIXED, prec
+    s.close()
+
+
+@pytest.mark.parametrize("cfg_name,prec,refine", [("mixed_n100", "BF16", 3),
+                                                  ("serve_n150", "F32", 1)])
+def test_mixed_large_configs_sampled(O, R, cfg_name, prec, refine):
+    """The synthetic N = 100 / N = 150 sets: ragged batch of 70 requests against the oracle,
+    velocity and pressure."""
+    cfg = get_config(cfg_name)
+    ts = make_tensor_set(cfg)
+    mu = draw_mu(cfg, 70)
+    s = R.Solver(ts)
+    th = s.theta(_dev(mu))
+    g = _mixed(R, s, th, prec, refine)
+    r = O.solve_batch(O.OracleSet(ts), mu, pressure_np=ts.Np)
+    assert np.all(g["status"] <= 1)
+    assert np.max(_rel(g["u"], r["u"])) <= TOL_MIXED
+    p = s.pressure(th, torch.as_tensor(g["u"]).cuda())
+    torch.cuda.synchronize()
+    assert np.all(p["pstatus"].cpu().numpy() == 0)
+    assert np.max(_rel(p["p"].cpu().numpy(), r["p"])) <= TOL_MIXED
+    s.close()
+
+
+def test_fp64_beyond_limit_is_unsupported(R):
+    ts = _random_set(100, seed=1)
+    s = R.Solver(ts)
+    th = s.theta(_dev(np.array([[0.1, 200.0]])))
+    with pytest.raises(R.RbError) as e:
+        s.solve(th)
+    assert e.value.code == R.RB_E_UNSUPPORTED
+    g = _mixed(R, s, th, "F32", 2)
+    assert g["status"][0] <= 1
     s.close()
 
 
