@@ -162,17 +162,43 @@ int rb_solve_batch(rb_ctx *ctx, int set, int B, int N, int ldu, const double *th
                    int *status, void *hip_stream);
 
 /*
- * rb_solve_uneven: like rb_solve_batch, but each request b has its own basis size
- * N[b] (device int [B]); rows of u0 / f_override / u have stride ldu >= the set's N.
- * Requests are grouped by basis size on the device and processed in one persistent launch
- * whose workgroups take tiles of same-size requests from a device work queue. Requests with
- * N[b] outside [1, set N] get status RB_ST_BADN.
- * Errors: as rb_solve_batch.
+ * rb_solve_uneven: like rb_solve_batch, but each request b has its own basis size N[b]
+ * (device int [B]; the nested basis of size N[b] is the leading block of the set's tensors);
+ * rows of u0 / f_override / u have stride ldu >= the set's N. Not part of the paper: a
+ * batching form for mixed basis sizes.
+ * The call copies N to the host (it waits for the work already queued on hip_stream), groups
+ * the requests by N (largest first, each group padded to whole 64-request tiles), gathers
+ * their inputs into library staging, runs the groups' Newton chains and scatters the results
+ * back in the caller's order. The group chains are captured into one HIP graph the second time
+ * the same shape (group sizes in tiles, options, tile shapes) occurs and replayed from then on
+ * (one graph launch per call, up to 4 group chains running concurrently); a shape seen for the
+ * first time runs as plain launches. The first time a (set, N, precision, batch size class)
+ * occurs, the autotuner times the candidate tile shapes on that group (synchronously) and
+ * keeps the fastest (environment RB_AUTOTUNE=0 disables it). Requests with N[b] outside
+ * [1, set N] get status RB_ST_BADN, iters 0 and u = 0.
+ * Errors: as rb_solve_batch (RB_E_INVAL also for ldu < the set's N).
  */
 int rb_solve_uneven(rb_ctx *ctx, int set, int B, const int *N, int ldu, const double *theta_a,
                     const double *theta_c, const double *theta_f, const double *f_override,
                     const double *u0, const rb_solve_opts *opts, double *u, int *iters,
                     int *status, void *hip_stream);
+
+/*
+ * rb_autotune: time the candidate tile shapes of a batch of B requests at basis size N with
+ * these coefficients (device theta_a [B][Q], theta_c [B][Qc], theta_f [B][Qf]) and keep the
+ * fastest for (set, N, opts->precision, batch size class ceil(log2(B/64))); later
+ * rb_solve_batch / rb_solve_uneven calls of that class use it. Candidates: 2, 4, 8 or 16 row
+ * splits per 64-request tile of the contraction, and (FP64, N <= 64) the pivot-row broadcast
+ * of the LU (readlane or LDS). Synchronous; produces no solution.
+ * rb_tuned_config: the shape in use for such a batch (defaults when never tuned: 8 splits,
+ * readlane), lu_variant 0 = readlane, 1 = LDS.
+ * Errors: RB_E_INVAL, RB_E_UNSUPPORTED (FP64 beyond RB_MAX_N_F64), RB_E_DEVICE.
+ */
+int rb_autotune(rb_ctx *ctx, int set, int B, int N, const double *theta_a,
+                const double *theta_c, const double *theta_f, const rb_solve_opts *opts,
+                void *hip_stream);
+int rb_tuned_config(rb_ctx *ctx, int set, int N, int precision, int B, int *nsplit,
+                    int *lu_variant);
 
 /*
  * rb_recover_pressure: a posteriori pressure for B velocity solutions at basis size N and

@@ -92,7 +92,7 @@ static __global__ void theta_kernel(const double* __restrict__ mu, int B, int Q,
 struct NewtonState {
   double* U;
   double* Fv;
-  double* Wv;              // [kSplit][Bp][NP] partial sums of A(mu) u
+  double* Wv;              // [nsplit][Bp][NP] partial sums of A(mu) u
   int64_t Bp;
   double* J;
   int* done;
@@ -101,6 +101,7 @@ struct NewtonState {
   double* dprev;           // previous update norm (stagnation test of the low-precision phase)
   int64_t mp;
   int NP;
+  int nsplit;              // partial sums per request in Wv / the mixed-precision partials
 };
 
 struct NewtonF64Args {
@@ -152,9 +153,9 @@ static __global__ void newton_init_kernel(NewtonF64Args a) {
 // ------------------------------------------------------------------ contraction ------
 // One MFMA-F64 contraction kernel serves the Jacobian of a Newton step, the FP64 residual of
 // the mixed-precision refinement and the pressure right-hand side. Workgroup g handles the
-// 64-request tile g / kSplit and the row split g % kSplit; with round-robin dispatch over the
-// 8 XCDs every workgroup of one XCD reads the same eighth of the packed operand, which
-// therefore stays in that XCD's L2. Wavefront w of the workgroup owns requests 16w..16w+15
+// 64-request tile g / nsplit and the row split g % nsplit (nsplit is a tuning knob, 8 by
+// default); with round-robin dispatch over the 8 XCDs and nsplit = 8 every workgroup of one
+// XCD reads the same eighth of the packed operand, which therefore stays in that XCD's L2. Wavefront w of the workgroup owns requests 16w..16w+15
 // of the tile and keeps its slice of W (the B operand) for one chunk of KC tensor k-steps in
 // registers, so the main loop touches no LDS; the four wavefronts walk the same row blocks
 // in the same order and share each A tile (one 512-byte line per k-step and row block)
@@ -173,9 +174,10 @@ static __global__ void newton_init_kernel(NewtonF64Args a) {
 //   residual: affine accumulator with weight 1, tensor accumulators with weight 1/2, so
 //             p = A(mu) u + C(mu)(u,u)  (the tensor part applied to u is 2 C(u,u));
 //   pressure: every accumulator with weight 1, p = A_sv u + C_sv(u,u).
-// Each workgroup writes its split's partial sums; the solve kernels add the kSplit partials.
+// Each workgroup writes its split's partial sums; the solve kernels add the nsplit partials.
 constexpr int kTile = 64;      // requests per workgroup tile (16 per wavefront)
-constexpr int kSplit = 8;      // row splits, one per XCD
+constexpr int kSplit = 8;      // default row splits, one per XCD
+constexpr int kMaxSplit = 16;  // largest split count (partial-sum buffers are sized for it)
 constexpr int kGroup = 4;      // row blocks per wavefront pass
 constexpr int kDepth = 4;      // k-steps of A operand in flight
 constexpr int kMaxKC = 64;     // longest tensor chunk held in registers
@@ -184,6 +186,7 @@ struct ContractArgs {
   const double* op;        // packed operand [nrb][nks][64]
   int nrb, nks, kA;        // row blocks, k-steps per row block (kA + nchunk*KC), affine k-steps
   int nchunk;              // tensor chunks of KC k-steps
+  int nsplit;              // row splits per tile (1..kMaxSplit)
   int R, N, M;             // rows m = j*R + i, M = R*N
   int Q, Qc, B;
   int64_t Bp;              // padded request count (multiple of kTile)
@@ -194,7 +197,7 @@ struct ContractArgs {
   const int* done;         // Newton flags [Bp] or nullptr
   double* J;               // Jacobian store [Bp][mp] or nullptr
   int64_t mp;
-  double* part;            // partial row sums [kSplit][Bp][ldp]
+  double* part;            // partial row sums [nsplit][Bp][ldp]
   int ldp;
 };
 
@@ -215,8 +218,8 @@ __global__ __launch_bounds__(kThreads) void contract_f64_kernel(ContractArgs a) 
   double* pl = ul + kTile * N;             // [kTile][R]
 
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int split = blockIdx.x % kSplit;
-  const int b0 = (blockIdx.x / kSplit) * kTile;
+  const int split = blockIdx.x % a.nsplit;
+  const int b0 = (blockIdx.x / a.nsplit) * kTile;
   if (a.done && __syncthreads_and(tid < kTile ? a.done[b0 + tid] : 1)) return;
 
   for (int idx = tid; idx < kTile * N; idx += kThreads) {
@@ -240,8 +243,8 @@ __global__ __launch_bounds__(kThreads) void contract_f64_kernel(ContractArgs a) 
   for (int q = 0; q < kMaxQc; ++q) tcv[q] = (bg < a.B && q < a.Qc) ? a.tc[(int64_t)bg * a.Qc + q] : 0.0;
   __syncthreads();
 
-  const int rb_lo = (int)((int64_t)split * a.nrb / kSplit);
-  const int rb_hi = (int)((int64_t)(split + 1) * a.nrb / kSplit);
+  const int rb_lo = (int)((int64_t)split * a.nrb / a.nsplit);
+  const int rb_hi = (int)((int64_t)(split + 1) * a.nrb / a.nsplit);
   const int col = bl;                      // accumulator column (request) of this lane
   const int nks = a.nks;
 
@@ -385,7 +388,7 @@ __global__ __launch_bounds__(kThreads) void lu_f64_kernel(NewtonF64Args a, int i
   if (lane < N) {
     double w = 0.0;
 #pragma unroll
-    for (int sp = 0; sp < kSplit; ++sp) w += a.s.Wv[((int64_t)sp * a.s.Bp + b) * NP + lane];
+    for (int sp = 0; sp < a.s.nsplit; ++sp) w += a.s.Wv[((int64_t)sp * a.s.Bp + b) * NP + lane];
     rhs = -(0.5 * (ju + w) - a.s.Fv[(int64_t)b * NP + lane]);   // F(u) = (J u + A u)/2 - f
   }
   bad |= !finite_val(rhs);
@@ -437,7 +440,7 @@ __global__ __launch_bounds__(kWave * W) void lu_f64_mw_kernel(NewtonF64Args a, i
   auto rhs_of = [&](int row, double ju) {
     double w = 0.0;
 #pragma unroll
-    for (int sp = 0; sp < kSplit; ++sp) w += a.s.Wv[((int64_t)sp * a.s.Bp + b) * NP + row];
+    for (int sp = 0; sp < a.s.nsplit; ++sp) w += a.s.Wv[((int64_t)sp * a.s.Bp + b) * NP + row];
     return -(0.5 * (ju + w) - a.s.Fv[(int64_t)b * NP + row]);
   };
   double nd2, nu2;
@@ -469,6 +472,69 @@ static __global__ void newton_final_kernel(NewtonF64Args a) {
   }
 }
 
+// ------------------------------------------------------------------ uneven batches ----
+// Staging of an uneven batch: requests regrouped by basis size (perm[r] = source request of
+// staging row r, -1 for padding rows, which get zero coefficients and so stop at once).
+struct UnevenIo {
+  int64_t Bs;              // staging rows (same-N groups, each padded to whole tiles)
+  int nbad;                // requests with an invalid N, listed at perm[Bs..Bs+nbad)
+  const int* perm;
+  int Q, Qc, Qf, Nm, ldu;
+  const double* ta;        // caller arrays [B][...]
+  const double* tc;
+  const double* tf;
+  const double* fover;     // [B][ldu] or nullptr
+  const double* u0;        // [B][ldu] or nullptr
+  double* ta_s;            // staging [Bs][Q], [Bs][Qc], [Bs][Qf] or [Bs][Nm], [Bs][Nm]
+  double* tc_s;
+  double* f_s;
+  double* u0_s;
+  double* u_s;             // staging results [Bs][Nm], iters / status [Bs]
+  int* it_s;
+  int* st_s;
+  double* u;               // caller results [B][ldu], [B], [B]
+  int* iters;
+  int* status;
+};
+
+static __global__ void uneven_gather_kernel(UnevenIo g) {
+  const int w = g.Q + g.Qc + (g.fover ? 0 : g.Qf);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < g.Bs * w; idx += stride) {
+    const int64_t r = idx / w;
+    const int k = idx - r * w;
+    const int b = g.perm[r];
+    if (k < g.Q) g.ta_s[r * g.Q + k] = b >= 0 ? g.ta[(int64_t)b * g.Q + k] : 0.0;
+    else if (k < g.Q + g.Qc) g.tc_s[r * g.Qc + k - g.Q] = b >= 0 ? g.tc[(int64_t)b * g.Qc + k - g.Q] : 0.0;
+    else g.f_s[r * g.Qf + k - g.Q - g.Qc] = b >= 0 ? g.tf[(int64_t)b * g.Qf + k - g.Q - g.Qc] : 0.0;
+  }
+  if (!g.fover && !g.u0) return;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < g.Bs * g.Nm; idx += stride) {
+    const int64_t r = idx / g.Nm;
+    const int i = idx - r * g.Nm;
+    const int b = g.perm[r];
+    if (g.fover) g.f_s[idx] = b >= 0 ? g.fover[(int64_t)b * g.ldu + i] : 0.0;
+    if (g.u0) g.u0_s[idx] = b >= 0 ? g.u0[(int64_t)b * g.ldu + i] : 0.0;
+  }
+}
+
+static __global__ void uneven_scatter_kernel(UnevenIo g) {
+  const int64_t rows = g.Bs + g.nbad;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < rows * g.ldu;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = idx / g.ldu;
+    const int i = idx - r * g.ldu;
+    const int b = g.perm[r];
+    if (b < 0) continue;
+    const bool ok = r < g.Bs;
+    g.u[(int64_t)b * g.ldu + i] = (ok && i < g.Nm) ? g.u_s[r * g.Nm + i] : 0.0;
+    if (i == 0) {
+      g.iters[b] = ok ? g.it_s[r] : 0;
+      g.status[b] = ok ? g.st_s[r] : 4;
+    }
+  }
+}
+
 // ------------------------------------------------------------------ pressure (FP64) ---
 // One wavefront per request: rhs = f_s(mu) - (A_sv u + C_sv(u,u)) (the contraction kernel's
 // partial sums), B(mu) = sum_q theta^b_q B_q, pivoted LU solve B(mu) p = rhs.
@@ -479,7 +545,8 @@ struct PressureF64Args {
   const double* tb;        // [B][Qb]
   const double* BpT;       // [Qb][Npm][Npm] transposed: BpT[q][c][i] = B_q[i][c]
   const double* Fs;        // [Qf][Npm]
-  const double* part;      // [kSplit][Bp][NPP] partial sums of A_sv u + C_sv(u,u)
+  const double* part;      // [nsplit][Bp][NPP] partial sums of A_sv u + C_sv(u,u)
+  int nsplit;
   double* p;               // [B][ldp]
   int* status;             // [B]
 };
@@ -511,7 +578,7 @@ __global__ __launch_bounds__(kThreads) void plu_f64_kernel(PressureF64Args a) {
   if (lane < Np) {
     for (int q = 0; q < a.Qf; ++q) rhs = fma(a.tf[(int64_t)b * a.Qf + q], a.Fs[(int64_t)q * a.Npm + lane], rhs);
 #pragma unroll
-    for (int sp = 0; sp < kSplit; ++sp) rhs -= a.part[((int64_t)sp * a.Bp + b) * NPP + lane];
+    for (int sp = 0; sp < a.nsplit; ++sp) rhs -= a.part[((int64_t)sp * a.Bp + b) * NPP + lane];
   }
   bad |= !finite_val(rhs);
   int flag = __builtin_amdgcn_readfirstlane(__any(bad) ? 3 : 0);

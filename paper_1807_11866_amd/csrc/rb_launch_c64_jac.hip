@@ -11,7 +11,7 @@ static int go(const ContractArgs& g, hipStream_t st) {
       hipFuncSetAttribute((const void*)contract_f64_kernel<kModeJac, KT>,
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
     return -3;
-  const int grid = (int)(g.Bp / kTile) * kSplit;
+  const int grid = (int)(g.Bp / kTile) * g.nsplit;
   hipLaunchKernelGGL((contract_f64_kernel<kModeJac, KT>), dim3(grid), dim3(kThreads), lds, st, g);
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }

@@ -12,7 +12,7 @@ static int go_c(const ContractLpArgs& g, hipStream_t st) {
       hipFuncSetAttribute((const void*)contract_lp_kernel<kBF16, KT>,
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
     return -3;
-  const int grid = (int)(g.Bp / kTile) * kSplit;
+  const int grid = (int)(g.Bp / kTile) * g.nsplit;
   hipLaunchKernelGGL((contract_lp_kernel<kBF16, KT>), dim3(grid), dim3(kThreads), lds, st, g);
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }

@@ -92,7 +92,8 @@ struct ContractLpArgs {
   const int* done;         // skip flags or nullptr
   float* J;                // FP32 Jacobians [Bp][mp], column-major per request
   int64_t mp;
-  float* part;             // partial A(mu) u [kSplit][Bp][ldp]
+  float* part;             // partial A(mu) u [nsplit][Bp][ldp]
+  int nsplit;
   int ldp;
 };
 
@@ -116,8 +117,8 @@ __global__ __launch_bounds__(kThreads) void contract_lp_kernel(ContractLpArgs a)
   float* pl = ul + kTile * N;              // [kTile][N]
 
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int split = blockIdx.x % kSplit;
-  const int b0 = (blockIdx.x / kSplit) * kTile;
+  const int split = blockIdx.x % a.nsplit;
+  const int b0 = (blockIdx.x / a.nsplit) * kTile;
   if (a.done && __syncthreads_and(tid < kTile ? a.done[b0 + tid] : 1)) return;
 
   for (int idx = tid; idx < kTile * N; idx += kThreads) {
@@ -168,8 +169,8 @@ __global__ __launch_bounds__(kThreads) void contract_lp_kernel(ContractLpArgs a)
 #pragma unroll
   for (int ks = 0; ks < KT; ++ks) wT[ks] = make(a.kA + ks);
 
-  const int rb_lo = (int)((int64_t)split * a.nrb / kSplit);
-  const int rb_hi = (int)((int64_t)(split + 1) * a.nrb / kSplit);
+  const int rb_lo = (int)((int64_t)split * a.nrb / a.nsplit);
+  const int rb_hi = (int)((int64_t)(split + 1) * a.nrb / a.nsplit);
   const int col = bl;
   const opnd* opb = static_cast<const opnd*>(a.op);
 
@@ -252,8 +253,8 @@ struct LpNewtonArgs {
   const double* H;         // [Nm][Nm] norm Gram or nullptr
   const float* J;          // [Bp][mp]
   int64_t mp;
-  const float* part;       // [kSplit][Bp][NP] A(mu) u (low-precision phase)
-  const double* partA;     // [kSplit][Bp][NP] A(mu) u + C(mu)(u,u) (FP64 refinement)
+  const float* part;       // [nsplit][Bp][NP] A(mu) u (low-precision phase)
+  const double* partA;     // [nsplit][Bp][NP] A(mu) u + C(mu)(u,u) (FP64 refinement)
   NewtonState s;           // FP64 iterates, f, flags
 };
 
@@ -289,12 +290,12 @@ __global__ __launch_bounds__(kThreads) void lu_lp_kernel(LpNewtonArgs a, int it)
     if (kRefine) {
       double g = 0.0;
 #pragma unroll
-      for (int sp = 0; sp < kSplit; ++sp) g += a.partA[((int64_t)sp * Bp + b) * NP + lane];
+      for (int sp = 0; sp < a.s.nsplit; ++sp) g += a.partA[((int64_t)sp * Bp + b) * NP + lane];
       rhs64 = -(g - a.s.Fv[(int64_t)b * NP + lane]);
     } else {
       float au = 0.f;
 #pragma unroll
-      for (int sp = 0; sp < kSplit; ++sp) au += a.part[((int64_t)sp * Bp + b) * NP + lane];
+      for (int sp = 0; sp < a.s.nsplit; ++sp) au += a.part[((int64_t)sp * Bp + b) * NP + lane];
       rhs64 = -(0.5 * (static_cast<double>(ju) + au) - a.s.Fv[(int64_t)b * NP + lane]);
     }
   }
@@ -355,12 +356,12 @@ __global__ __launch_bounds__(kWave * W) void lu_lp_mw_kernel(LpNewtonArgs a, int
     if (refine) {
       double g = 0.0;
 #pragma unroll
-      for (int sp = 0; sp < kSplit; ++sp) g += a.partA[((int64_t)sp * Bp + b) * NP + row];
+      for (int sp = 0; sp < a.s.nsplit; ++sp) g += a.partA[((int64_t)sp * Bp + b) * NP + row];
       return -(g - f);
     }
     float au = 0.f;
 #pragma unroll
-    for (int sp = 0; sp < kSplit; ++sp) au += a.part[((int64_t)sp * Bp + b) * NP + row];
+    for (int sp = 0; sp < a.s.nsplit; ++sp) au += a.part[((int64_t)sp * Bp + b) * NP + row];
     return -(0.5 * (static_cast<double>(ju) + au) - f);
   };
   double nd2, nu2;

@@ -6,10 +6,12 @@
 #include <cstdlib>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <map>
 #include <memory>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <utility>
 #include <vector>
 
@@ -63,6 +65,21 @@ struct Workspace {
   DevBuf buf;            // Newton state of the last batch on this stream (see NewtonState)
 };
 
+// Tile shape of one (set, N, precision, batch size class): row splits per 64-request tile of
+// the contraction and the pivot-row broadcast of the one-wavefront FP64 LU.
+struct Tune {
+  int nsplit = 8;
+  bool lu_lds = false;
+};
+
+// A captured uneven-batch graph and the shape it was captured for.
+struct GraphEntry {
+  std::vector<int64_t> key;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  uint64_t last = 0;
+};
+
 }  // namespace
 
 struct TimedLaunch {
@@ -80,6 +97,18 @@ struct rb_ctx {
   bool lu_lds = false;                  // pivot-row broadcast through LDS instead of readlane
   std::vector<TimedLaunch> timed;       // recorded, not yet read
   std::vector<hipEvent_t> event_pool;
+  // autotuner results: (set, N, precision, batch size class) -> tile shape
+  std::map<std::tuple<int, int, int, int>, Tune> tune;
+  bool autotune = true;
+  // uneven batches: pinned staging of the per-request sizes / permutation, capture streams,
+  // graph cache and the shapes seen once (captured on their second occurrence)
+  int* pin = nullptr;
+  size_t pin_cap = 0;
+  hipStream_t cap_stream = nullptr;
+  std::vector<hipStream_t> branches;
+  std::vector<GraphEntry> graphs;
+  std::vector<std::vector<int64_t>> seen;
+  uint64_t tick = 0;
 };
 
 namespace {
@@ -243,12 +272,12 @@ int workspace(rb_ctx* c, void* stream, size_t bytes, Workspace** out) {
 }
 
 // Carve the Newton state for Bp (padded) requests out of one workspace allocation.
-size_t newton_state_bytes(int64_t Bp, int NP, int64_t mp) {
-  return (size_t)(Bp * mp + (2 + rb::kSplit) * Bp * NP + Bp) * sizeof(double) +
+size_t newton_state_bytes(int64_t Bp, int NP, int64_t mp, int nsplit) {
+  return (size_t)(Bp * mp + (2 + nsplit) * Bp * NP + Bp) * sizeof(double) +
          (size_t)3 * Bp * sizeof(int) + 256;
 }
 
-rb::NewtonState carve_state(void* base, int64_t Bp, int NP, int64_t mp) {
+rb::NewtonState carve_state(void* base, int64_t Bp, int NP, int64_t mp, int nsplit) {
   rb::NewtonState s;
   double* d = (double*)base;
   s.J = d;
@@ -258,7 +287,7 @@ rb::NewtonState carve_state(void* base, int64_t Bp, int NP, int64_t mp) {
   s.Fv = d;
   d += Bp * NP;
   s.Wv = d;
-  d += rb::kSplit * Bp * NP;
+  d += nsplit * Bp * NP;
   s.dprev = d;
   d += Bp;
   int* ip = (int*)d;
@@ -268,7 +297,20 @@ rb::NewtonState carve_state(void* base, int64_t Bp, int NP, int64_t mp) {
   s.mp = mp;
   s.NP = NP;
   s.Bp = Bp;
+  s.nsplit = nsplit;
   return s;
+}
+
+// Mixed-precision buffers (FP32 Jacobians and partial sums, FP64 residual partials).
+size_t lp_extra_bytes(int64_t Bp, int NP, int64_t mp, int nsplit) {
+  return (size_t)(Bp * mp + nsplit * Bp * NP + 64) * sizeof(float) + 512 +
+         (size_t)nsplit * Bp * NP * sizeof(double);
+}
+
+size_t solve_bytes(int64_t Bp, int NP, int64_t mp, int nsplit, int precision) {
+  size_t b = newton_state_bytes(Bp, NP, mp, nsplit);
+  if (precision != RB_PREC_F64) b += lp_extra_bytes(Bp, NP, mp, nsplit);
+  return (size_t)ceil_to((int64_t)b, 256);
 }
 
 // Register row length of the LU kernels: multiples of 4 up to 64 (one wavefront per system),
@@ -312,12 +354,12 @@ struct LaunchTimer {
 
 // Enqueue a whole batched Newton solve: init, max_iter x (Jacobian kernel, LU kernel),
 // final copy-out. Converged requests are skipped by both kernels through the done flags.
-int enqueue_newton(rb_ctx* c, const rb::NewtonF64Args& a, hipStream_t st) {
+int enqueue_newton(rb_ctx* c, const rb::NewtonF64Args& a, bool lu_lds, hipStream_t st) {
   const int NP = a.s.NP;
   const int64_t Bp = a.s.Bp;
   rb::ContractArgs g;
   g.op = a.op;
-  g.nrb = a.nrb; g.nks = a.nks; g.kA = a.nks_s; g.nchunk = a.nchunk;
+  g.nrb = a.nrb; g.nks = a.nks; g.kA = a.nks_s; g.nchunk = a.nchunk; g.nsplit = a.s.nsplit;
   g.R = a.N; g.N = a.N; g.M = a.N * a.N;
   g.Q = a.Q; g.Qc = a.Qc; g.B = a.B; g.Bp = Bp;
   g.ta = a.ta; g.tc = a.tc;
@@ -332,7 +374,7 @@ int enqueue_newton(rb_ctx* c, const rb::NewtonF64Args& a, hipStream_t st) {
       if (int rc = launch_rc(rb::launch::contract_f64(rb::kModeJac, g, st), "jacobian")) return rc;
     }
     LaunchTimer t(c, FAM_LU, st);
-    if (int rc = launch_rc(rb::launch::lu_f64(NP, a, it, c->lu_lds, st), "lu")) return rc;
+    if (int rc = launch_rc(rb::launch::lu_f64(NP, a, it, lu_lds, st), "lu")) return rc;
   }
   hipLaunchKernelGGL(rb::newton_final_kernel, dim3(launch_grid((int64_t)a.B * a.ldu)),
                      dim3(256), 0, st, a);
@@ -345,17 +387,16 @@ int enqueue_newton(rb_ctx* c, const rb::NewtonF64Args& a, hipStream_t st) {
 // refine_steps refinement steps, each with the FP64 residual and the Jacobian of the last
 // low-precision step, until the update is below tol.
 int enqueue_newton_lp(rb_ctx* c, Set* s, const rb::NewtonF64Args& a, bool bf16, int refine,
-                      Workspace* w, hipStream_t st) {
+                      char* base, hipStream_t st) {
   const int N = a.N, NP = a.s.NP;
   const int64_t Bp = a.s.Bp, mp = a.s.mp;
   Pack *pf, *pl;
   if (int rc = solve_pack_f64(c, s, N, &pf)) return rc;
   if (int rc = solve_pack_lp(c, s, N, bf16, &pl)) return rc;
-  // low-precision buffers follow the FP64 state in the workspace
-  char* base = (char*)w->buf.p + newton_state_bytes(Bp, NP, mp);
-  float* J32 = (float*)base;
+  const int nsplit = a.s.nsplit;
+  float* J32 = (float*)base;               // low-precision buffers (lp_extra_bytes)
   float* part32 = J32 + Bp * mp;
-  double* partA = (double*)(part32 + rb::kSplit * Bp * NP + 64);
+  double* partA = (double*)(part32 + nsplit * Bp * NP + 64);
   partA = (double*)(((uintptr_t)partA + 255) & ~(uintptr_t)255);
 
   rb::ContractLpArgs gl;
@@ -365,12 +406,13 @@ int enqueue_newton_lp(rb_ctx* c, Set* s, const rb::NewtonF64Args& a, bool bf16, 
   gl.ta = a.ta; gl.tc = a.tc; gl.U = a.s.U; gl.ldU = NP;
   gl.done = a.s.done;
   gl.J = J32; gl.mp = mp;
-  gl.part = part32; gl.ldp = NP;
+  gl.part = part32; gl.ldp = NP; gl.nsplit = nsplit;
   const int KT = pl->nks - pl->nks_s;
 
   rb::ContractArgs gr;                      // FP64 residual
   gr.op = (const double*)pf->buf.p;
   gr.nrb = pf->nrb; gr.nks = pf->nks; gr.kA = pf->nks_s; gr.nchunk = pf->nchunk;
+  gr.nsplit = nsplit;
   gr.R = N; gr.N = N; gr.M = N * N;
   gr.Q = a.Q; gr.Qc = a.Qc; gr.B = a.B; gr.Bp = Bp;
   gr.ta = a.ta; gr.tc = a.tc; gr.U = a.s.U; gr.ldU = NP;
@@ -411,10 +453,162 @@ int enqueue_newton_lp(rb_ctx* c, Set* s, const rb::NewtonF64Args& a, bool bf16, 
   return RB_OK;
 }
 
-size_t lp_extra_bytes(int64_t Bp, int NP, int64_t mp) {
-  return (size_t)(Bp * mp + rb::kSplit * Bp * NP + 64) * sizeof(float) + 512 +
-         (size_t)rb::kSplit * Bp * NP * sizeof(double);
+// Shape class of a batch for the tuning table: ceil(log2(tiles)).
+int batch_class(int64_t Bp) {
+  int t = 0;
+  while (((int64_t)rb::kTile << t) < Bp) ++t;
+  return t;
 }
+
+Tune tune_for(rb_ctx* c, int set, int N, int precision, int64_t Bp) {
+  auto it = c->tune.find(std::make_tuple(set, N, precision, batch_class(Bp)));
+  if (it != c->tune.end()) return it->second;
+  Tune t;
+  t.lu_lds = c->lu_lds;
+  return t;
+}
+
+int check_opts(const char* fn, const rb_solve_opts& o) {
+  if (!(o.tol >= 0.0) || o.max_iter < 1 || o.max_iter > 1000)
+    return fail(RB_E_INVAL, "%s: bad options (tol=%g, max_iter=%d)", fn, o.tol, o.max_iter);
+  if (o.precision != RB_PREC_F64 && o.precision != RB_PREC_F32 && o.precision != RB_PREC_BF16)
+    return fail(RB_E_INVAL, "%s: unknown precision %d", fn, o.precision);
+  if (o.precision != RB_PREC_F64 && (o.refine_steps < 0 || o.refine_steps > 100))
+    return fail(RB_E_INVAL, "%s: refine_steps=%d", fn, o.refine_steps);
+  return RB_OK;
+}
+
+// Newton arguments of one same-N batch whose state lives at `region` (solve_bytes long).
+rb::NewtonF64Args make_args(Set* s, Pack* pk, int N, int B, int ldu, const rb_solve_opts& o,
+                            const double* ta, const double* tc, const double* tf,
+                            const double* fover, const double* u0, double* u, int* iters,
+                            int* status, char* region, int nsplit) {
+  rb::NewtonF64Args a;
+  a.op = (const double*)pk->buf.p;
+  a.nrb = pk->nrb; a.nks_s = pk->nks_s; a.nks = pk->nks; a.nchunk = pk->nchunk;
+  a.N = N; a.Nm = s->N; a.Q = s->Q; a.Qc = s->Qc; a.Qf = s->Qf; a.B = B; a.ldu = ldu;
+  a.maxit = o.max_iter; a.tol = o.tol;
+  a.ta = ta; a.tc = tc; a.tf = tf; a.fover = fover; a.u0 = u0;
+  a.F = (const double*)s->F.p;
+  a.H = s->hasH ? (const double*)s->H.p : nullptr;
+  a.u = u; a.iters = iters; a.status = status;
+  const int64_t Bp = ceil_to(B, rb::kTile);
+  a.s = carve_state(region, Bp, np_bucket(N), ceil_to((int64_t)N * N, 16), nsplit);
+  return a;
+}
+
+int enqueue_solve(rb_ctx* c, Set* s, const rb::NewtonF64Args& a, const rb_solve_opts& o,
+                  const Tune& t, char* region, hipStream_t st) {
+  if (o.precision == RB_PREC_F64) return enqueue_newton(c, a, t.lu_lds, st);
+  char* lp = region + newton_state_bytes(a.s.Bp, a.s.NP, a.s.mp, a.s.nsplit);
+  return enqueue_newton_lp(c, s, a, o.precision == RB_PREC_BF16, o.refine_steps, lp, st);
+}
+
+// Autotuner. On the batch at hand (its state region sized for kMaxSplit partial sums), time
+// the first Newton contraction for each row-split count and, for the one-wavefront FP64 LU,
+// both pivot-row broadcasts; record the fastest shape for (set, N, precision, batch class).
+// Synchronous on st; must not run under stream capture.
+int autotune_batch(rb_ctx* c, Set* s, int set, rb::NewtonF64Args a, const rb_solve_opts& o,
+                   char* region, hipStream_t st, Tune* out) {
+  const int N = a.N, NP = a.s.NP;
+  const int64_t Bp = a.s.Bp, mp = a.s.mp;
+  const bool lp = o.precision != RB_PREC_F64, bf16 = o.precision == RB_PREC_BF16;
+  Pack* pl = nullptr;
+  if (lp)
+    if (int rc = solve_pack_lp(c, s, N, bf16, &pl)) return rc;
+  hipEvent_t e0 = take_event(c), e1 = take_event(c);
+  if (!e0 || !e1) return fail(RB_E_DEVICE, "autotune: cannot create events");
+  auto release = [&](int rc) {
+    c->event_pool.push_back(e0);
+    c->event_pool.push_back(e1);
+    return rc;
+  };
+  a.s = carve_state(region, Bp, NP, mp, rb::kMaxSplit);
+  char* lpb = region + newton_state_bytes(Bp, NP, mp, rb::kMaxSplit);
+  auto contract = [&](int nsplit) -> int {
+    a.s.nsplit = nsplit;
+    if (!lp) {
+      rb::ContractArgs g;
+      g.op = a.op;
+      g.nrb = a.nrb; g.nks = a.nks; g.kA = a.nks_s; g.nchunk = a.nchunk; g.nsplit = nsplit;
+      g.R = N; g.N = N; g.M = N * N;
+      g.Q = a.Q; g.Qc = a.Qc; g.B = a.B; g.Bp = Bp;
+      g.ta = a.ta; g.tc = a.tc; g.U = a.s.U; g.ldU = NP;
+      g.done = a.s.done; g.J = a.s.J; g.mp = mp;
+      g.part = a.s.Wv; g.ldp = NP;
+      return launch_rc(rb::launch::contract_f64(rb::kModeJac, g, st), "autotune contraction");
+    }
+    rb::ContractLpArgs g;
+    g.op = pl->buf.p;
+    g.nrb = pl->nrb; g.kA = pl->nks_s; g.nks = pl->nks;
+    g.N = N; g.M = N * N; g.Q = a.Q; g.Qc = a.Qc; g.B = a.B; g.Bp = Bp;
+    g.ta = a.ta; g.tc = a.tc; g.U = a.s.U; g.ldU = NP;
+    g.done = a.s.done; g.J = (float*)lpb; g.mp = mp;
+    g.part = (float*)lpb + Bp * mp; g.ldp = NP; g.nsplit = nsplit;
+    return launch_rc(rb::launch::contract_lp(bf16, pl->nks - pl->nks_s, g, st),
+                     "autotune contraction");
+  };
+  auto timed = [&](auto&& launch, float* ms) -> int {
+    for (int rep = 0; rep < 2; ++rep) {          // the second run is timed
+      HIP_TRY(hipEventRecord(e0, st));
+      if (int rc = launch()) return rc;
+      HIP_TRY(hipEventRecord(e1, st));
+    }
+    HIP_TRY(hipEventSynchronize(e1));
+    HIP_TRY(hipEventElapsedTime(ms, e0, e1));
+    return RB_OK;
+  };
+  hipLaunchKernelGGL(rb::newton_init_kernel, dim3(launch_grid(Bp * NP)), dim3(256), 0, st, a);
+  Tune best;
+  best.lu_lds = c->lu_lds;
+  float best_ms = 1e30f;
+  for (int ns : {2, 4, 8, 16}) {
+    if (ns > 2 && ns > a.nrb) continue;          // more splits than row blocks
+    float ms = 0.f;
+    if (int rc = timed([&] { return contract(ns); }, &ms)) return release(rc);
+    if (ms < best_ms) {
+      best_ms = ms;
+      best.nsplit = ns;
+    }
+  }
+  if (!lp && NP <= 64) {
+    float lu_ms[2] = {0.f, 0.f};
+    for (int v = 0; v < 2; ++v) {
+      hipLaunchKernelGGL(rb::newton_init_kernel, dim3(launch_grid(Bp * NP)), dim3(256), 0, st, a);
+      if (int rc = contract(best.nsplit)) return release(rc);
+      if (int rc = timed([&] { return launch_rc(rb::launch::lu_f64(NP, a, 0, v == 1, st),
+                                                "autotune lu"); }, &lu_ms[v]))
+        return release(rc);
+    }
+    best.lu_lds = lu_ms[1] < lu_ms[0];
+  }
+  c->tune[std::make_tuple(set, N, o.precision, batch_class(Bp))] = best;
+  *out = best;
+  return release(RB_OK);
+}
+
+int ensure_pinned(rb_ctx* c, size_t ints) {
+  if (c->pin_cap >= ints) return RB_OK;
+  if (c->pin) HIP_TRY(hipHostFree(c->pin));
+  c->pin = nullptr;
+  c->pin_cap = 0;
+  HIP_TRY(hipHostMalloc((void**)&c->pin, ints * sizeof(int), hipHostMallocDefault));
+  c->pin_cap = ints;
+  return RB_OK;
+}
+
+int ensure_streams(rb_ctx* c, int n) {
+  if (!c->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  while ((int)c->branches.size() < n) {
+    hipStream_t b;
+    HIP_TRY(hipStreamCreateWithFlags(&b, hipStreamNonBlocking));
+    c->branches.push_back(b);
+  }
+  return RB_OK;
+}
+
+constexpr int kBranches = 4;      // concurrent bucket chains inside an uneven-batch graph
+constexpr size_t kGraphCache = 16;
 
 }  // namespace
 
@@ -434,6 +628,7 @@ int rb_create(int device, size_t hbm_budget_bytes, rb_ctx** out) {
   c->device = device;
   c->budget = hbm_budget_bytes;
   if (const char* v = getenv("RB_LU_BCAST")) c->lu_lds = (strcmp(v, "lds") == 0);
+  if (const char* v = getenv("RB_AUTOTUNE")) c->autotune = (strcmp(v, "0") != 0);
   *out = c;
   g_err.clear();
   return RB_OK;
@@ -456,6 +651,13 @@ int rb_destroy(rb_ctx* c) {
     (void)hipEventDestroy(t.stop);
   }
   for (auto e : c->event_pool) (void)hipEventDestroy(e);
+  for (auto& g : c->graphs) {
+    (void)hipGraphExecDestroy(g.exec);
+    (void)hipGraphDestroy(g.graph);
+  }
+  for (auto b : c->branches) (void)hipStreamDestroy(b);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  if (c->pin) (void)hipHostFree(c->pin);
   delete c;
   return RB_OK;
 }
@@ -543,13 +745,7 @@ int rb_solve_batch(rb_ctx* c, int set, int B, int N, int ldu, const double* ta,
   if (ldu < N) return fail(RB_E_INVAL, "rb_solve_batch: ldu=%d < N=%d", ldu, N);
   rb_solve_opts o = {1e-12, 10, RB_PREC_F64, 1};
   if (opts) o = *opts;
-  if (!(o.tol >= 0.0) || o.max_iter < 1 || o.max_iter > 1000)
-    return fail(RB_E_INVAL, "rb_solve_batch: bad options (tol=%g, max_iter=%d)", o.tol,
-                o.max_iter);
-  if (o.precision != RB_PREC_F64 && o.precision != RB_PREC_F32 && o.precision != RB_PREC_BF16)
-    return fail(RB_E_INVAL, "rb_solve_batch: unknown precision %d", o.precision);
-  if (o.precision != RB_PREC_F64 && (o.refine_steps < 0 || o.refine_steps > 100))
-    return fail(RB_E_INVAL, "rb_solve_batch: refine_steps=%d", o.refine_steps);
+  if (int rc = check_opts("rb_solve_batch", o)) return rc;
   if (o.precision == RB_PREC_F64 && N > RB_MAX_N_F64)
     return fail(RB_E_UNSUPPORTED, "rb_solve_batch: FP64 solves take N <= %d (N=%d)",
                 RB_MAX_N_F64, N);
@@ -560,33 +756,267 @@ int rb_solve_batch(rb_ctx* c, int set, int B, int N, int ldu, const double* ta,
   if (int rc = use_device(c)) return rc;
   Pack* pk;
   if (int rc = solve_pack_f64(c, s, N, &pk)) return rc;
-  const int64_t mp = ceil_to((int64_t)N * N, 16);
-  const int NP = np_bucket(N);
   const int64_t Bp = ceil_to(B, rb::kTile);
+  const Tune t = tune_for(c, set, N, o.precision, Bp);
   Workspace* w;
-  size_t ws = newton_state_bytes(Bp, NP, mp);
-  if (o.precision != RB_PREC_F64) ws += lp_extra_bytes(Bp, NP, mp);
-  if (int rc = workspace(c, stream, ws, &w)) return rc;
-  rb::NewtonF64Args a;
-  a.op = (const double*)pk->buf.p;
-  a.nrb = pk->nrb; a.nks_s = pk->nks_s; a.nks = pk->nks; a.nchunk = pk->nchunk;
-  a.N = N; a.Nm = s->N; a.Q = s->Q; a.Qc = s->Qc; a.Qf = s->Qf; a.B = B; a.ldu = ldu;
-  a.maxit = o.max_iter; a.tol = o.tol;
-  a.ta = ta; a.tc = tc; a.tf = tf; a.fover = fover; a.u0 = u0;
-  a.F = (const double*)s->F.p;
-  a.H = s->hasH ? (const double*)s->H.p : nullptr;
-  a.u = u; a.iters = iters; a.status = status;
-  a.s = carve_state(w->buf.p, Bp, NP, mp);
-  if (o.precision == RB_PREC_F64) return enqueue_newton(c, a, (hipStream_t)stream);
-  return enqueue_newton_lp(c, s, a, o.precision == RB_PREC_BF16, o.refine_steps, w,
-                           (hipStream_t)stream);
+  if (int rc = workspace(c, stream, solve_bytes(Bp, np_bucket(N), ceil_to((int64_t)N * N, 16),
+                                                t.nsplit, o.precision), &w))
+    return rc;
+  char* region = (char*)w->buf.p;
+  rb::NewtonF64Args a = make_args(s, pk, N, B, ldu, o, ta, tc, tf, fover, u0, u, iters, status,
+                                  region, t.nsplit);
+  return enqueue_solve(c, s, a, o, t, region, (hipStream_t)stream);
 }
 
-int rb_solve_uneven(rb_ctx* c, int, int, const int*, int, const double*, const double*,
-                    const double*, const double*, const double*, const rb_solve_opts*,
-                    double*, int*, int*, void*) {
+int rb_autotune(rb_ctx* c, int set, int B, int N, const double* ta, const double* tc,
+                const double* tf, const rb_solve_opts* opts, void* stream) {
+  if (!c) return fail(RB_E_INVAL, "rb_autotune: NULL context");
+  Set* s = get_set(c, set);
+  if (!s) return fail(RB_E_INVAL, "rb_autotune: unknown set %d", set);
+  if (B < 1 || N < 1 || N > s->N) return fail(RB_E_INVAL, "rb_autotune: B=%d N=%d", B, N);
+  rb_solve_opts o = {1e-12, 10, RB_PREC_F64, 1};
+  if (opts) o = *opts;
+  if (int rc = check_opts("rb_autotune", o)) return rc;
+  if (o.precision == RB_PREC_F64 && N > RB_MAX_N_F64)
+    return fail(RB_E_UNSUPPORTED, "rb_autotune: FP64 solves take N <= %d", RB_MAX_N_F64);
+  if (!ta || !tc || !tf) return fail(RB_E_INVAL, "rb_autotune: NULL array");
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (int rc = use_device(c)) return rc;
+  Pack* pk;
+  if (int rc = solve_pack_f64(c, s, N, &pk)) return rc;
+  const int64_t Bp = ceil_to(B, rb::kTile);
+  Workspace* w;
+  if (int rc = workspace(c, stream, solve_bytes(Bp, np_bucket(N), ceil_to((int64_t)N * N, 16),
+                                                rb::kMaxSplit, o.precision), &w))
+    return rc;
+  char* region = (char*)w->buf.p;
+  rb::NewtonF64Args a = make_args(s, pk, N, B, N, o, ta, tc, tf, nullptr, nullptr, nullptr,
+                                  nullptr, nullptr, region, rb::kMaxSplit);
+  Tune t;
+  return autotune_batch(c, s, set, a, o, region, (hipStream_t)stream, &t);
+}
+
+int rb_tuned_config(rb_ctx* c, int set, int N, int precision, int B, int* nsplit,
+                    int* lu_variant) {
+  if (!c || !nsplit || !lu_variant) return fail(RB_E_INVAL, "rb_tuned_config: NULL argument");
+  std::lock_guard<std::mutex> lk(c->mu);
+  const Tune t = tune_for(c, set, N, precision, ceil_to(B < 1 ? 1 : B, rb::kTile));
+  *nsplit = t.nsplit;
+  *lu_variant = t.lu_lds ? 1 : 0;
+  return RB_OK;
+}
+
+int rb_solve_uneven(rb_ctx* c, int set, int B, const int* Nd, int ldu, const double* ta,
+                    const double* tc, const double* tf, const double* fover, const double* u0,
+                    const rb_solve_opts* opts, double* u, int* iters, int* status,
+                    void* stream) {
   if (!c) return fail(RB_E_INVAL, "rb_solve_uneven: NULL context");
-  return fail(RB_E_UNSUPPORTED, "rb_solve_uneven: not available in this build");
+  Set* s = get_set(c, set);
+  if (!s) return fail(RB_E_INVAL, "rb_solve_uneven: unknown set %d", set);
+  if (B < 0) return fail(RB_E_INVAL, "rb_solve_uneven: B=%d", B);
+  if (ldu < s->N) return fail(RB_E_INVAL, "rb_solve_uneven: ldu=%d < set N=%d", ldu, s->N);
+  rb_solve_opts o = {1e-12, 10, RB_PREC_F64, 1};
+  if (opts) o = *opts;
+  if (int rc = check_opts("rb_solve_uneven", o)) return rc;
+  if (B == 0) return RB_OK;
+  if (!Nd || !ta || !tc || (!tf && !fover) || !u || !iters || !status)
+    return fail(RB_E_INVAL, "rb_solve_uneven: NULL array");
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (int rc = use_device(c)) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  const int Nm = s->N;
+
+  // 1. per-request sizes to the host (drains st, so the pinned buffer is free again)
+  if (int rc = ensure_pinned(c, (size_t)3 * B + 64 * 160)) return rc;
+  int* hN = c->pin;
+  HIP_TRY(hipMemcpyAsync(hN, Nd, (size_t)B * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+
+  // 2. same-N groups, largest N first; invalid sizes listed separately
+  std::map<int, std::vector<int>, std::greater<int>> groups;
+  std::vector<int> bad;
+  for (int b = 0; b < B; ++b) {
+    const int n = hN[b];
+    if (n < 1 || n > Nm) bad.push_back(b);
+    else groups[n].push_back(b);
+  }
+  if (o.precision == RB_PREC_F64 && !groups.empty() && groups.begin()->first > RB_MAX_N_F64)
+    return fail(RB_E_UNSUPPORTED, "rb_solve_uneven: FP64 solves take N <= %d (N=%d)",
+                RB_MAX_N_F64, groups.begin()->first);
+
+  // 3. layout: staging arrays, then one state region per group (sized for kMaxSplit so the
+  //    autotuner can run in place)
+  struct Group {
+    int N;
+    int64_t cnt, Bp, off;
+    size_t region;
+    Pack* pk;
+    Tune t;
+  };
+  std::vector<Group> gs;
+  int64_t Bs = 0;
+  for (auto& kv : groups) {
+    Group g;
+    g.N = kv.first;
+    g.cnt = (int64_t)kv.second.size();
+    g.Bp = ceil_to(g.cnt, rb::kTile);
+    g.off = Bs;
+    Bs += g.Bp;
+    gs.push_back(g);
+  }
+  const int nbad = (int)bad.size();
+  const int fw = fover ? Nm : s->Qf;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o2 = off;
+    off += (size_t)ceil_to((int64_t)bytes, 256);
+    return o2;
+  };
+  const size_t o_ta = take(Bs * s->Q * 8), o_tc = take(Bs * s->Qc * 8), o_f = take(Bs * fw * 8);
+  const size_t o_u0 = take(u0 ? Bs * Nm * 8 : 8), o_u = take(Bs * Nm * 8);
+  const size_t o_it = take(Bs * 4), o_st = take(Bs * 4), o_perm = take((Bs + nbad) * 4);
+  for (auto& g : gs)
+    g.region = take(solve_bytes(g.Bp, np_bucket(g.N), ceil_to((int64_t)g.N * g.N, 16),
+                                rb::kMaxSplit, o.precision));
+  Workspace* w;
+  if (int rc = workspace(c, stream, off, &w)) return rc;
+  char* base = (char*)w->buf.p;
+  rb::UnevenIo io;
+  io.Bs = Bs; io.nbad = nbad; io.perm = (const int*)(base + o_perm);
+  io.Q = s->Q; io.Qc = s->Qc; io.Qf = s->Qf; io.Nm = Nm; io.ldu = ldu;
+  io.ta = ta; io.tc = tc; io.tf = tf; io.fover = fover; io.u0 = u0;
+  io.ta_s = (double*)(base + o_ta); io.tc_s = (double*)(base + o_tc);
+  io.f_s = (double*)(base + o_f); io.u0_s = (double*)(base + o_u0);
+  io.u_s = (double*)(base + o_u); io.it_s = (int*)(base + o_it); io.st_s = (int*)(base + o_st);
+  io.u = u; io.iters = iters; io.status = status;
+
+  // 4. permutation to the device, gather into staging
+  int* hp = c->pin + B;
+  {
+    int64_t r = 0;
+    for (size_t i = 0; i < gs.size(); ++i) {
+      const auto& src = groups[gs[i].N];
+      for (int64_t k = 0; k < gs[i].Bp; ++k) hp[r++] = k < gs[i].cnt ? src[k] : -1;
+    }
+    for (int b : bad) hp[r++] = b;
+  }
+  HIP_TRY(hipMemcpyAsync(base + o_perm, hp, (size_t)(Bs + nbad) * sizeof(int),
+                         hipMemcpyHostToDevice, st));
+  if (Bs > 0)
+    hipLaunchKernelGGL(rb::uneven_gather_kernel, dim3(launch_grid(Bs * Nm)), dim3(256), 0, st, io);
+  HIP_TRY(hipGetLastError());
+
+  // 5. operands and tile shapes (outside any capture: packing and tuning synchronise)
+  auto args_of = [&](Group& g, int nsplit) {
+    const int64_t r0 = g.off;
+    return make_args(s, g.pk, g.N, (int)g.Bp, Nm, o, io.ta_s + r0 * s->Q, io.tc_s + r0 * s->Qc,
+                     fover ? nullptr : io.f_s + r0 * s->Qf, fover ? io.f_s + r0 * Nm : nullptr,
+                     u0 ? io.u0_s + r0 * Nm : nullptr, io.u_s + r0 * Nm, io.it_s + r0,
+                     io.st_s + r0, base + g.region, nsplit);
+  };
+  for (auto& g : gs) {
+    if (int rc = solve_pack_f64(c, s, g.N, &g.pk)) return rc;
+    if (o.precision != RB_PREC_F64) {
+      Pack* pl;
+      if (int rc = solve_pack_lp(c, s, g.N, o.precision == RB_PREC_BF16, &pl)) return rc;
+    }
+    const auto key = std::make_tuple(set, g.N, o.precision, batch_class(g.Bp));
+    if (c->autotune && !c->tune.count(key)) {
+      if (int rc = autotune_batch(c, s, set, args_of(g, rb::kMaxSplit), o, base + g.region, st,
+                                  &g.t))
+        return rc;
+    }
+    g.t = tune_for(c, set, g.N, o.precision, g.Bp);
+  }
+
+  // 6. the group chains: replayed from a captured graph when this shape has been seen before
+  std::vector<int64_t> key = {set, o.precision, o.max_iter, o.refine_steps,
+                              (int64_t)(uintptr_t)base, Bs, fover ? 1 : 0, u0 ? 1 : 0};
+  int64_t tolbits;
+  std::memcpy(&tolbits, &o.tol, 8);
+  key.push_back(tolbits);
+  for (auto& g : gs) {
+    key.push_back(g.N);
+    key.push_back(g.Bp);
+    key.push_back(g.t.nsplit);
+    key.push_back(g.t.lu_lds);
+  }
+  auto run_group = [&](Group& g, hipStream_t gst) {
+    return enqueue_solve(c, s, args_of(g, g.t.nsplit), o, g.t, base + g.region, gst);
+  };
+  GraphEntry* hit = nullptr;
+  for (auto& e : c->graphs)
+    if (e.key == key) hit = &e;
+  const bool seen = std::find(c->seen.begin(), c->seen.end(), key) != c->seen.end();
+  if (!hit && seen && !gs.empty()) {
+    if (int rc = ensure_streams(c, kBranches)) return rc;
+    const bool timing = c->timing;
+    c->timing = false;                       // no event records inside the graph
+    hipEvent_t fork = nullptr;
+    std::vector<hipEvent_t> joins;
+    hipGraph_t graph = nullptr;
+    int rc = RB_OK;
+    HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    if (hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventRecord(fork, c->cap_stream) != hipSuccess)
+      rc = fail(RB_E_DEVICE, "rb_solve_uneven: capture fork failed");
+    const int nb = std::min<int>(kBranches, (int)gs.size());
+    for (int i = 0; i < nb && rc == RB_OK; ++i)
+      if (hipStreamWaitEvent(c->branches[i], fork, 0) != hipSuccess)
+        rc = fail(RB_E_DEVICE, "rb_solve_uneven: capture fork failed");
+    for (size_t i = 0; i < gs.size() && rc == RB_OK; ++i) rc = run_group(gs[i], c->branches[i % nb]);
+    for (int i = 0; i < nb && rc == RB_OK; ++i) {
+      hipEvent_t j = nullptr;
+      if (hipEventCreateWithFlags(&j, hipEventDisableTiming) != hipSuccess ||
+          hipEventRecord(j, c->branches[i]) != hipSuccess ||
+          hipStreamWaitEvent(c->cap_stream, j, 0) != hipSuccess)
+        rc = fail(RB_E_DEVICE, "rb_solve_uneven: capture join failed");
+      if (j) joins.push_back(j);
+    }
+    const hipError_t ec = hipStreamEndCapture(c->cap_stream, &graph);
+    c->timing = timing;
+    if (fork) (void)hipEventDestroy(fork);
+    for (auto j : joins) (void)hipEventDestroy(j);
+    if (rc == RB_OK && ec != hipSuccess)
+      rc = fail(RB_E_DEVICE, "rb_solve_uneven: capture failed: %s", hipGetErrorString(ec));
+    hipGraphExec_t exec = nullptr;
+    if (rc == RB_OK && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess)
+      rc = fail(RB_E_DEVICE, "rb_solve_uneven: graph instantiation failed");
+    if (rc != RB_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc;
+    }
+    if (c->graphs.size() >= kGraphCache) {
+      auto lru = std::min_element(c->graphs.begin(), c->graphs.end(),
+                                  [](const GraphEntry& x, const GraphEntry& y) { return x.last < y.last; });
+      (void)hipGraphExecDestroy(lru->exec);
+      (void)hipGraphDestroy(lru->graph);
+      c->graphs.erase(lru);
+    }
+    GraphEntry e;
+    e.key = key;
+    e.graph = graph;
+    e.exec = exec;
+    c->graphs.push_back(e);
+    hit = &c->graphs.back();
+  }
+  if (hit) {
+    hit->last = ++c->tick;
+    HIP_TRY(hipGraphLaunch(hit->exec, st));
+  } else {
+    for (auto& g : gs)
+      if (int rc = run_group(g, st)) return rc;
+    if (!seen) {
+      if (c->seen.size() >= 64) c->seen.erase(c->seen.begin());
+      c->seen.push_back(key);
+    }
+  }
+
+  // 7. results back to the caller's order
+  hipLaunchKernelGGL(rb::uneven_scatter_kernel, dim3(launch_grid((Bs + nbad) * ldu)), dim3(256),
+                     0, st, io);
+  HIP_TRY(hipGetLastError());
+  return RB_OK;
 }
 
 int rb_recover_pressure(rb_ctx* c, int set, int B, int N, int Np, int ldu, int ldp,
@@ -623,13 +1053,13 @@ int rb_recover_pressure(rb_ctx* c, int set, int B, int N, int Np, int ldu, int l
   g.U = u; g.ldU = ldu;
   g.done = nullptr;
   g.J = nullptr; g.mp = 0;
-  g.part = (double*)w->buf.p; g.ldp = NPP;
+  g.part = (double*)w->buf.p; g.ldp = NPP; g.nsplit = rb::kSplit;
   rb::PressureF64Args a;
   a.Np = Np; a.Npm = s->Np; a.Qf = s->Qf; a.Qb = s->Qb; a.B = B; a.ldp = ldp; a.Bp = Bp;
   a.tf = tf; a.tb = tb;
   a.BpT = (const double*)s->BpT.p;
   a.Fs = (const double*)s->Fs.p;
-  a.part = g.part;
+  a.part = g.part; a.nsplit = rb::kSplit;
   a.p = p; a.status = status;
   LaunchTimer t(c, FAM_PRESSURE, st);
   if (int rc = launch_rc(rb::launch::contract_f64(rb::kModePressure, g, st), "pressure"))

@@ -19,8 +19,8 @@ RB_ST_CONVERGED, RB_ST_MAXIT, RB_ST_SINGULAR, RB_ST_NONFINITE, RB_ST_BADN = 0, 1
 RB_PREC_F64, RB_PREC_F32, RB_PREC_BF16 = 0, 1, 2
 
 EXPORTED = ("rb_create", "rb_destroy", "rb_last_error", "rb_hbm_used", "rb_load_tensors",
-            "rb_theta", "rb_solve_batch", "rb_solve_uneven", "rb_recover_pressure",
-            "rb_timing_enable", "rb_timing_read")
+            "rb_theta", "rb_solve_batch", "rb_solve_uneven", "rb_autotune", "rb_tuned_config",
+            "rb_recover_pressure", "rb_timing_enable", "rb_timing_read")
 
 _dp = ct.POINTER(ct.c_double)
 _vp = ct.c_void_p
@@ -68,6 +68,10 @@ def load(path=None):
                                    [ct.POINTER(SolveOpts)] + [_vp] * 3 + [_vp])
     lib.rb_solve_uneven.argtypes = ([_vp, ct.c_int, ct.c_int, _vp, ct.c_int] + [_vp] * 5 +
                                     [ct.POINTER(SolveOpts)] + [_vp] * 3 + [_vp])
+    lib.rb_autotune.argtypes = ([_vp, ct.c_int, ct.c_int, ct.c_int] + [_vp] * 3 +
+                                [ct.POINTER(SolveOpts), _vp])
+    lib.rb_tuned_config.argtypes = [_vp, ct.c_int, ct.c_int, ct.c_int, ct.c_int,
+                                    ct.POINTER(ct.c_int), ct.POINTER(ct.c_int)]
     lib.rb_recover_pressure.argtypes = ([_vp] + [ct.c_int] * 6 + [_vp] * 7 + [_vp])
     lib.rb_timing_enable.argtypes = [_vp, ct.c_int]
     lib.rb_timing_read.argtypes = [_vp, ct.c_char_p, ct.POINTER(ct.c_double),
@@ -168,6 +172,20 @@ def rb_solve_uneven(ctx, set_id, B, N, ldu, theta_a, theta_c, theta_f, f_overrid
                                   _ptr(iters), _ptr(status), _stream(stream)))
 
 
+def rb_autotune(ctx, set_id, B, N, theta_a, theta_c, theta_f, opts, stream=None):
+    _check(load().rb_autotune(ctx, set_id, int(B), int(N), _ptr(theta_a), _ptr(theta_c),
+                              _ptr(theta_f), ct.byref(opts) if opts is not None else None,
+                              _stream(stream)))
+
+
+def rb_tuned_config(ctx, set_id, N, precision, B):
+    """(row splits per tile, LU variant 0 = readlane / 1 = LDS) used for such a batch."""
+    ns, lv = ct.c_int(0), ct.c_int(0)
+    _check(load().rb_tuned_config(ctx, set_id, int(N), int(precision), int(B), ct.byref(ns),
+                                  ct.byref(lv)))
+    return ns.value, lv.value
+
+
 def rb_recover_pressure(ctx, set_id, B, N, Np, ldu, ldp, theta_a, theta_c, theta_f, theta_b,
                         u, p, status, stream=None):
     _check(load().rb_recover_pressure(ctx, set_id, int(B), int(N), int(Np), int(ldu),
@@ -250,6 +268,13 @@ class Solver:
         rb_solve_uneven(self.ctx, self.set, B, Nreq, self.N, th["ta"], th["tc"], th["tf"],
                         f_override, u0, opts, out["u"], out["iters"], out["status"], stream)
         return out
+
+    def autotune(self, th, N=None, tol=1e-12, max_iter=10, precision=RB_PREC_F64,
+                 refine_steps=1, stream=None):
+        N = self.N if N is None else N
+        rb_autotune(self.ctx, self.set, th["ta"].shape[0], N, th["ta"], th["tc"], th["tf"],
+                    make_opts(tol, max_iter, precision, refine_steps), stream)
+        return rb_tuned_config(self.ctx, self.set, N, precision, th["ta"].shape[0])
 
     def pressure(self, th, u, N=None, Np=None, out=None, stream=None):
         t = self.torch
