@@ -214,6 +214,73 @@ int rb_recover_pressure(rb_ctx *ctx, int set, int B, int N, int Np, int ldu, int
                         const double *theta_b, const double *u, double *p, int *status,
                         void *hip_stream);
 
+/* ------------------------------------------------------------------ serving --------- */
+/*
+ * Continuous-batching server on top of one context and tensor set (not part of the paper: a
+ * serving form of the online stage). rb_server_submit queues requests (mu, N) and returns at
+ * once; a worker thread forms batches from whatever has arrived whenever one of its `lanes`
+ * (HIP streams, each with its own device buffers) is free, so requests that arrive while
+ * others are on the GPU are admitted as soon as a lane and the HBM budget allow, and the
+ * batches of different lanes overlap on the device. A batch is grouped by N and each group is
+ * solved as a same-N batch (theta(mu) on the device, Newton, optionally the pressure), with
+ * the tile shapes a same-N rb_solve_batch call of that size would use; a request's result
+ * does not depend on the other requests of its batch. rb_server_poll hands back finished
+ * results (with the latency from submission to the moment the worker saw the batch finish).
+ * The tensor set stays resident; each lane keeps its buffers and workspace between batches.
+ * Stop every server of a context before rb_destroy.
+ */
+#define RB_ST_FAILED 5   /* server: the batch could not be run (see rb_server_counters.error) */
+
+typedef struct rb_server rb_server;
+
+typedef struct {
+    int precision;            /* RB_PREC_*                                                  */
+    int refine_steps;         /* mixed precisions: refinement steps                         */
+    int max_iter;             /* Newton iteration limit                                     */
+    double tol;               /* Newton tolerance                                           */
+    int max_batch;            /* requests per batch (1..65536)                              */
+    int lanes;                /* batches in flight at once (1..4)                           */
+    size_t hbm_budget_bytes;  /* workspace of the batches in flight (0: no limit): a batch is
+                                 cut (halved until it fits) beside the batches in flight, or
+                                 waits for them to finish; alone it runs at any size        */
+    int pressure;             /* 1: also recover the pressure (set must have pressure data) */
+} rb_server_opts;
+
+typedef struct {
+    double alpha, re;         /* mu = (angle of attack [rad], Reynolds number)              */
+    int N;                    /* basis size, 1 <= N <= set N (else status RB_ST_BADN)       */
+    long long tag;            /* caller's label, returned with the result                   */
+} rb_request;
+
+typedef struct {
+    long long ticket, tag;
+    int N, status, iters, pstatus;
+    double latency_ms;        /* submission -> batch completion seen by the worker          */
+    double u[RB_MAX_N];       /* velocity coefficients (first N valid, rest 0)              */
+    double p[RB_MAX_NP];      /* pressure coefficients (first Np valid) if opts.pressure    */
+} rb_result;
+
+typedef struct {
+    long long submitted, completed, batches;
+    double p50_ms, p99_ms, max_ms;   /* latency quantiles over the completed requests      */
+    double mean_batch;               /* requests per batch                                  */
+    double first_submit_s, last_done_s;   /* on the server's clock (seconds since start)   */
+    size_t hbm_inflight_peak;        /* largest workspace estimate of batches in flight    */
+    char error[256];                 /* last batch failure, empty if none                  */
+} rb_server_counters;
+
+/* Errors: RB_E_INVAL (bad set / opts), RB_E_NOMEM (lane buffers), RB_E_DEVICE. */
+int rb_server_start(rb_ctx *ctx, int set, const rb_server_opts *opts, rb_server **out);
+/* Queue n requests; tickets[i] receives the ticket of reqs[i] (may be NULL). */
+int rb_server_submit(rb_server *srv, const rb_request *reqs, int n, long long *tickets);
+/* Move up to max finished results into out; *n_out = how many. Never blocks. */
+int rb_server_poll(rb_server *srv, rb_result *out, int max, int *n_out);
+/* Latency / throughput counters so far. */
+int rb_server_stats(rb_server *srv, rb_server_counters *out);
+/* Finish every queued request, stop the worker and free the lanes (results not yet polled
+ * are dropped). */
+int rb_server_stop(rb_server *srv);
+
 /*
  * Kernel timing for measurement (used by the benchmark): while enabled, every launch of the
  * kernel families "jacobian" (MFMA Jacobian + residual contraction), "lu" (pivoted LU solve +

@@ -7,10 +7,14 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
 #include <map>
 #include <memory>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <tuple>
 #include <utility>
 #include <vector>
@@ -449,6 +453,45 @@ int enqueue_newton_lp(rb_ctx* c, Set* s, const rb::NewtonF64Args& a, bool bf16, 
   }
   hipLaunchKernelGGL(rb::newton_final_kernel, dim3(launch_grid((int64_t)a.B * a.ldu)),
                      dim3(256), 0, st, a);
+  HIP_TRY(hipGetLastError());
+  return RB_OK;
+}
+
+size_t pressure_bytes(int B, int Np) {
+  return (size_t)rb::kSplit * ceil_to(B, rb::kTile) * np_bucket(Np) * sizeof(double);
+}
+
+// Pressure recovery of B requests at (N, Np) (eqn sup-vvar): the pressure-operand
+// contraction (A_sv u + C_sv(u,u), kSplit partial sums at `part`, pressure_bytes long) and
+// the pivoted LU solve B(mu) p = f_s - A_sv u - C_sv(u,u).
+int enqueue_pressure(rb_ctx* c, Set* s, int B, int N, int Np, int ldu, int ldp,
+                     const double* ta, const double* tc, const double* tf, const double* tb,
+                     const double* u, double* p, int* status, char* part, hipStream_t st) {
+  Pack* pk;
+  if (int rc = press_pack_f64(c, s, N, Np, &pk)) return rc;
+  const int NPP = np_bucket(Np);
+  const int64_t Bp = ceil_to(B, rb::kTile);
+  rb::ContractArgs g;
+  g.op = (const double*)pk->buf.p;
+  g.nrb = pk->nrb; g.nks = pk->nks; g.kA = pk->nks_s; g.nchunk = pk->nchunk;
+  g.R = Np; g.N = N; g.M = Np * N;
+  g.Q = s->Q; g.Qc = s->Qc; g.B = B; g.Bp = Bp;
+  g.ta = ta; g.tc = tc;
+  g.U = u; g.ldU = ldu;
+  g.done = nullptr;
+  g.J = nullptr; g.mp = 0;
+  g.part = (double*)part; g.ldp = NPP; g.nsplit = rb::kSplit;
+  rb::PressureF64Args a;
+  a.Np = Np; a.Npm = s->Np; a.Qf = s->Qf; a.Qb = s->Qb; a.B = B; a.ldp = ldp; a.Bp = Bp;
+  a.tf = tf; a.tb = tb;
+  a.BpT = (const double*)s->BpT.p;
+  a.Fs = (const double*)s->Fs.p;
+  a.part = g.part; a.nsplit = rb::kSplit;
+  a.p = p; a.status = status;
+  LaunchTimer t(c, FAM_PRESSURE, st);
+  if (int rc = launch_rc(rb::launch::contract_f64(rb::kModePressure, g, st), "pressure"))
+    return rc;
+  if (int rc = launch_rc(rb::launch::plu_f64(NPP, a, c->lu_lds, st), "pressure lu")) return rc;
   HIP_TRY(hipGetLastError());
   return RB_OK;
 }
@@ -1037,36 +1080,10 @@ int rb_recover_pressure(rb_ctx* c, int set, int B, int N, int Np, int ldu, int l
     return fail(RB_E_INVAL, "rb_recover_pressure: NULL array");
   std::lock_guard<std::mutex> lk(c->mu);
   if (int rc = use_device(c)) return rc;
-  Pack* pk;
-  if (int rc = press_pack_f64(c, s, N, Np, &pk)) return rc;
-  const int NPP = np_bucket(Np);
-  const int64_t Bp = ceil_to(B, rb::kTile);
   Workspace* w;
-  if (int rc = workspace(c, stream, (size_t)rb::kSplit * Bp * NPP * sizeof(double), &w)) return rc;
-  hipStream_t st = (hipStream_t)stream;
-  rb::ContractArgs g;
-  g.op = (const double*)pk->buf.p;
-  g.nrb = pk->nrb; g.nks = pk->nks; g.kA = pk->nks_s; g.nchunk = pk->nchunk;
-  g.R = Np; g.N = N; g.M = Np * N;
-  g.Q = s->Q; g.Qc = s->Qc; g.B = B; g.Bp = Bp;
-  g.ta = ta; g.tc = tc;
-  g.U = u; g.ldU = ldu;
-  g.done = nullptr;
-  g.J = nullptr; g.mp = 0;
-  g.part = (double*)w->buf.p; g.ldp = NPP; g.nsplit = rb::kSplit;
-  rb::PressureF64Args a;
-  a.Np = Np; a.Npm = s->Np; a.Qf = s->Qf; a.Qb = s->Qb; a.B = B; a.ldp = ldp; a.Bp = Bp;
-  a.tf = tf; a.tb = tb;
-  a.BpT = (const double*)s->BpT.p;
-  a.Fs = (const double*)s->Fs.p;
-  a.part = g.part; a.nsplit = rb::kSplit;
-  a.p = p; a.status = status;
-  LaunchTimer t(c, FAM_PRESSURE, st);
-  if (int rc = launch_rc(rb::launch::contract_f64(rb::kModePressure, g, st), "pressure"))
-    return rc;
-  if (int rc = launch_rc(rb::launch::plu_f64(NPP, a, c->lu_lds, st), "pressure lu")) return rc;
-  HIP_TRY(hipGetLastError());
-  return RB_OK;
+  if (int rc = workspace(c, stream, pressure_bytes(B, Np), &w)) return rc;
+  return enqueue_pressure(c, s, B, N, Np, ldu, ldp, ta, tc, tf, tb, u, p, status,
+                          (char*)w->buf.p, (hipStream_t)stream);
 }
 
 int rb_timing_enable(rb_ctx* c, int enable) {
@@ -1104,6 +1121,427 @@ int rb_timing_read(rb_ctx* c, const char* family, double* total_ms, int* launche
   c->timed.swap(keep);
   *total_ms = tot;
   *launches = n;
+  return RB_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ serving ----------
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct Pending {
+  long long ticket, tag;
+  int N;
+  double alpha, re;
+  Clock::time_point t_submit;
+};
+
+// One lane: a stream, its device buffers for max_batch requests and pinned host mirrors.
+struct Lane {
+  hipStream_t st = nullptr;
+  hipEvent_t done = nullptr;
+  bool busy = false;
+  size_t need = 0;                    // workspace estimate of the batch in flight
+  std::vector<Pending> batch;         // in the order of the device rows (grouped by N)
+  DevBuf d_mu, d_ta, d_tc, d_tf, d_tb, d_u, d_p, d_int;
+  double* h_mu = nullptr;             // pinned [cap][2]
+  double* h_u = nullptr;              // pinned [cap][Nm]
+  double* h_p = nullptr;              // pinned [cap][Np]
+  int* h_int = nullptr;               // pinned [3][cap]: iters, status, pstatus
+};
+
+}  // namespace
+
+struct rb_server {
+  rb_ctx* c = nullptr;
+  int set = 0;
+  Set* s = nullptr;
+  rb_server_opts o{};
+  int cap = 0;
+  std::vector<Lane> lanes;
+  std::thread worker;
+  std::mutex qm;                      // queue, results, stats
+  std::condition_variable qcv;
+  std::deque<Pending> queue;
+  std::deque<rb_result> results;
+  bool stopping = false;
+  long long next_ticket = 1, submitted = 0, completed = 0, batches = 0;
+  std::vector<double> lat_ms;
+  Clock::time_point t0;
+  double first_submit_s = -1.0, last_done_s = 0.0;
+  size_t inflight = 0, inflight_peak = 0;
+  std::string error;
+};
+
+namespace {
+
+// Workspace of one batch: per N group the Newton state (tile shapes of a same-N batch of that
+// size) and, with pressure, the pressure partial sums.
+size_t batch_bytes(rb_server* v, const std::vector<std::pair<int, int>>& groups) {
+  size_t b = 0;
+  for (auto& g : groups) {
+    const int N = g.first;
+    const int64_t Bp = ceil_to(g.second, rb::kTile);
+    const Tune t = tune_for(v->c, v->set, N, v->o.precision, Bp);
+    b += solve_bytes(Bp, np_bucket(N), ceil_to((int64_t)N * N, 16), t.nsplit, v->o.precision);
+    if (v->o.pressure) b += (size_t)ceil_to((int64_t)pressure_bytes(g.second, v->s->Np), 256);
+  }
+  return b;
+}
+
+// Launch one batch on a lane (caller holds the context lock). Rows are grouped by N, largest
+// first; each group runs as a same-N batch on the lane's stream.
+int launch_batch(rb_server* v, Lane& L) {
+  rb_ctx* c = v->c;
+  Set* s = v->s;
+  const int Nm = s->N, Np = s->Np, B = (int)L.batch.size();
+  for (int i = 0; i < B; ++i) {
+    L.h_mu[2 * i] = L.batch[i].alpha;
+    L.h_mu[2 * i + 1] = L.batch[i].re;
+  }
+  HIP_TRY(hipMemcpyAsync(L.d_mu.p, L.h_mu, (size_t)B * 2 * sizeof(double), hipMemcpyHostToDevice,
+                         L.st));
+  const int Qb = Np > 0 ? s->Qb : 1;
+  double* ta = (double*)L.d_ta.p;
+  double* tc = (double*)L.d_tc.p;
+  double* tf = (double*)L.d_tf.p;
+  double* tb = (double*)L.d_tb.p;
+  hipLaunchKernelGGL(rb::theta_kernel, dim3((B + 255) / 256), dim3(256), 0, L.st,
+                     (const double*)L.d_mu.p, B, s->Q, s->Qc, s->Qf, Qb, ta, tc, tf,
+                     Np > 0 ? tb : nullptr);
+  std::vector<std::pair<int, int>> groups;   // (N, count), rows contiguous
+  for (int i = 0; i < B;) {
+    int j = i;
+    while (j < B && L.batch[j].N == L.batch[i].N) ++j;
+    groups.push_back({L.batch[i].N, j - i});
+    i = j;
+  }
+  Workspace* w;
+  if (int rc = workspace(c, L.st, batch_bytes(v, groups), &w)) return rc;
+  char* base = (char*)w->buf.p;
+  double* u = (double*)L.d_u.p;
+  double* p = (double*)L.d_p.p;
+  int* it = (int*)L.d_int.p;
+  int* stt = it + v->cap;
+  int* pst = it + 2 * v->cap;
+  rb_solve_opts o = {v->o.tol, v->o.max_iter, v->o.precision, v->o.refine_steps};
+  int r0 = 0;
+  for (auto& g : groups) {
+    const int N = g.first, n = g.second;
+    const int64_t Bp = ceil_to(n, rb::kTile);
+    Pack* pk;
+    if (int rc = solve_pack_f64(c, s, N, &pk)) return rc;
+    const Tune t = tune_for(c, v->set, N, o.precision, Bp);
+    rb::NewtonF64Args a =
+        make_args(s, pk, N, n, Nm, o, ta + (int64_t)r0 * s->Q, tc + (int64_t)r0 * s->Qc,
+                  tf + (int64_t)r0 * s->Qf, nullptr, nullptr, u + (int64_t)r0 * Nm, it + r0,
+                  stt + r0, base, t.nsplit);
+    if (int rc = enqueue_solve(c, s, a, o, t, base, L.st)) return rc;
+    base += solve_bytes(Bp, np_bucket(N), ceil_to((int64_t)N * N, 16), t.nsplit, o.precision);
+    if (v->o.pressure) {
+      if (int rc = enqueue_pressure(c, s, n, N, Np, Nm, Np, ta + (int64_t)r0 * s->Q,
+                                    tc + (int64_t)r0 * s->Qc, tf + (int64_t)r0 * s->Qf,
+                                    tb + (int64_t)r0 * s->Qb, u + (int64_t)r0 * Nm,
+                                    p + (int64_t)r0 * Np, pst + r0, base, L.st))
+        return rc;
+      base += (size_t)ceil_to((int64_t)pressure_bytes(n, Np), 256);
+    }
+    r0 += n;
+  }
+  HIP_TRY(hipMemcpyAsync(L.h_u, u, (size_t)B * Nm * sizeof(double), hipMemcpyDeviceToHost, L.st));
+  HIP_TRY(hipMemcpyAsync(L.h_int, it, (size_t)3 * v->cap * sizeof(int), hipMemcpyDeviceToHost, L.st));
+  if (v->o.pressure)
+    HIP_TRY(hipMemcpyAsync(L.h_p, p, (size_t)B * Np * sizeof(double), hipMemcpyDeviceToHost, L.st));
+  HIP_TRY(hipEventRecord(L.done, L.st));
+  return RB_OK;
+}
+
+// Results of a finished lane into the result queue (caller holds v->qm).
+void harvest(rb_server* v, Lane& L, bool failed) {
+  const int Nm = v->s->N, Np = v->s->Np;
+  const auto now = Clock::now();
+  for (size_t i = 0; i < L.batch.size(); ++i) {
+    const Pending& q = L.batch[i];
+    rb_result r;
+    std::memset(&r, 0, sizeof r);
+    r.ticket = q.ticket;
+    r.tag = q.tag;
+    r.N = q.N;
+    if (failed) {
+      r.status = RB_ST_FAILED;
+      r.pstatus = RB_ST_FAILED;
+    } else {
+      r.iters = L.h_int[i];
+      r.status = L.h_int[v->cap + i];
+      r.pstatus = v->o.pressure ? L.h_int[2 * v->cap + i] : 0;
+      for (int k = 0; k < q.N; ++k) r.u[k] = L.h_u[(size_t)i * Nm + k];
+      if (v->o.pressure)
+        for (int k = 0; k < Np; ++k) r.p[k] = L.h_p[(size_t)i * Np + k];
+    }
+    r.latency_ms = std::chrono::duration<double, std::milli>(now - q.t_submit).count();
+    v->lat_ms.push_back(r.latency_ms);
+    v->results.push_back(r);
+  }
+  v->completed += (long long)L.batch.size();
+  v->last_done_s = std::chrono::duration<double>(now - v->t0).count();
+  v->inflight -= L.need;
+  L.batch.clear();
+  L.busy = false;
+}
+
+void bad_request(rb_server* v, const Pending& q) {
+  rb_result r;
+  std::memset(&r, 0, sizeof r);
+  r.ticket = q.ticket;
+  r.tag = q.tag;
+  r.N = q.N;
+  r.status = RB_ST_BADN;
+  r.pstatus = RB_ST_BADN;
+  r.latency_ms = std::chrono::duration<double, std::milli>(Clock::now() - q.t_submit).count();
+  v->lat_ms.push_back(r.latency_ms);
+  v->results.push_back(r);
+  ++v->completed;
+}
+
+void serve(rb_server* v) {
+  (void)hipSetDevice(v->c->device);
+  std::unique_lock<std::mutex> lk(v->qm);
+  for (;;) {
+    bool progress = false;
+    // 1. retire finished lanes
+    for (auto& L : v->lanes) {
+      if (!L.busy) continue;
+      const hipError_t q = hipEventQuery(L.done);
+      if (q == hipErrorNotReady) continue;
+      if (q != hipSuccess) v->error = hipGetErrorString(q);
+      harvest(v, L, q != hipSuccess);
+      progress = true;
+    }
+    // 2. admit: a free lane takes what has arrived, up to max_batch and the HBM budget
+    for (auto& L : v->lanes) {
+      if (L.busy || v->queue.empty()) continue;
+      std::vector<Pending> take;
+      while (!v->queue.empty() && (int)take.size() < v->cap) {
+        Pending q = v->queue.front();
+        v->queue.pop_front();
+        if (q.N < 1 || q.N > v->s->N) { bad_request(v, q); progress = true; continue; }
+        take.push_back(q);
+      }
+      if (take.empty()) continue;
+      std::stable_sort(take.begin(), take.end(),
+                       [](const Pending& x, const Pending& y) { return x.N > y.N; });
+      auto groups_of = [](const std::vector<Pending>& t, size_t n) {
+        std::vector<std::pair<int, int>> g;
+        for (size_t i = 0; i < n; ++i) {
+          if (g.empty() || g.back().first != t[i].N) g.push_back({t[i].N, 0});
+          ++g.back().second;
+        }
+        return g;
+      };
+      std::lock_guard<std::mutex> ck(v->c->mu);   // tuning table, workspaces, launches
+      size_t n = take.size();
+      size_t need = batch_bytes(v, groups_of(take, n));
+      const size_t budget = v->o.hbm_budget_bytes;
+      while (budget && n > 1 && v->inflight + need > budget) {   // cut to what fits
+        n = n / 2;
+        need = batch_bytes(v, groups_of(take, n));
+      }
+      if (budget && v->inflight + need > budget && v->inflight > 0) n = 0;   // wait for room
+      for (size_t i = take.size(); i-- > n;) v->queue.push_front(take[i]);
+      if (n == 0) continue;
+      take.resize(n);
+      // keep the N order of the (possibly cut) batch: rows grouped by N
+      L.batch = std::move(take);
+      L.need = need;
+      L.busy = true;
+      v->inflight += need;
+      v->inflight_peak = std::max(v->inflight_peak, v->inflight);
+      ++v->batches;
+      const int rc = launch_batch(v, L);
+      if (rc != RB_OK) {
+        v->error = g_err;
+        (void)hipStreamSynchronize(L.st);
+        harvest(v, L, true);
+      }
+      progress = true;
+    }
+    bool idle = v->queue.empty();
+    for (auto& L : v->lanes) idle = idle && !L.busy;
+    if (v->stopping && idle) break;
+    if (!progress) {
+      bool any_busy = false;
+      for (auto& L : v->lanes) any_busy = any_busy || L.busy;
+      // lanes in flight: poll again shortly; nothing to do: sleep until a submission
+      if (any_busy) v->qcv.wait_for(lk, std::chrono::microseconds(20));
+      else v->qcv.wait(lk, [&] { return v->stopping || !v->queue.empty(); });
+    }
+  }
+}
+
+void free_lanes(rb_server* v) {
+  for (auto& L : v->lanes) {
+    for (DevBuf* b : {&L.d_mu, &L.d_ta, &L.d_tc, &L.d_tf, &L.d_tb, &L.d_u, &L.d_p, &L.d_int})
+      dev_free(v->c, *b);
+    for (void* h : {(void*)L.h_mu, (void*)L.h_u, (void*)L.h_p, (void*)L.h_int})
+      if (h) (void)hipHostFree(h);
+    if (L.done) (void)hipEventDestroy(L.done);
+    if (L.st) {
+      auto it = v->c->ws.find((void*)L.st);
+      if (it != v->c->ws.end()) {
+        dev_free(v->c, it->second.buf);
+        v->c->ws.erase(it);
+      }
+      (void)hipStreamDestroy(L.st);
+    }
+  }
+  v->lanes.clear();
+}
+
+}  // namespace
+
+extern "C" {
+
+int rb_server_start(rb_ctx* c, int set, const rb_server_opts* opts, rb_server** out) {
+  if (!c || !opts || !out) return fail(RB_E_INVAL, "rb_server_start: NULL argument");
+  *out = nullptr;
+  Set* s = get_set(c, set);
+  if (!s) return fail(RB_E_INVAL, "rb_server_start: unknown set %d", set);
+  const rb_server_opts& o = *opts;
+  rb_solve_opts so = {o.tol, o.max_iter, o.precision, o.refine_steps};
+  if (int rc = check_opts("rb_server_start", so)) return rc;
+  if (o.precision == RB_PREC_F64 && s->N > RB_MAX_N_F64)
+    return fail(RB_E_UNSUPPORTED, "rb_server_start: FP64 serving takes set N <= %d",
+                RB_MAX_N_F64);
+  if (o.max_batch < 1 || o.max_batch > 65536 || o.lanes < 1 || o.lanes > 4)
+    return fail(RB_E_INVAL, "rb_server_start: max_batch=%d lanes=%d", o.max_batch, o.lanes);
+  if (o.pressure && s->Np == 0)
+    return fail(RB_E_INVAL, "rb_server_start: set %d has no pressure data", set);
+  std::unique_ptr<rb_server> v(new rb_server);
+  v->c = c;
+  v->set = set;
+  v->s = s;
+  v->o = o;
+  v->cap = o.max_batch;
+  v->t0 = Clock::now();
+  {
+    std::lock_guard<std::mutex> ck(c->mu);
+    if (int rc = use_device(c)) return rc;
+    const size_t cap = v->cap, Nm = s->N, Np = std::max(1, s->Np);
+    v->lanes.resize(o.lanes);
+    for (auto& L : v->lanes) {
+      int rc = RB_OK;
+      if (hipStreamCreateWithFlags(&L.st, hipStreamNonBlocking) != hipSuccess ||
+          hipEventCreateWithFlags(&L.done, hipEventDisableTiming) != hipSuccess)
+        rc = fail(RB_E_DEVICE, "rb_server_start: stream/event creation failed");
+      if (!rc) rc = dev_alloc(c, L.d_mu, cap * 2 * 8);
+      if (!rc) rc = dev_alloc(c, L.d_ta, cap * s->Q * 8);
+      if (!rc) rc = dev_alloc(c, L.d_tc, cap * s->Qc * 8);
+      if (!rc) rc = dev_alloc(c, L.d_tf, cap * s->Qf * 8);
+      if (!rc) rc = dev_alloc(c, L.d_tb, cap * std::max(1, s->Qb) * 8);
+      if (!rc) rc = dev_alloc(c, L.d_u, cap * Nm * 8);
+      if (!rc) rc = dev_alloc(c, L.d_p, cap * Np * 8);
+      if (!rc) rc = dev_alloc(c, L.d_int, cap * 3 * 4);
+      if (!rc && (hipHostMalloc((void**)&L.h_mu, cap * 2 * 8, hipHostMallocDefault) != hipSuccess ||
+                  hipHostMalloc((void**)&L.h_u, cap * Nm * 8, hipHostMallocDefault) != hipSuccess ||
+                  hipHostMalloc((void**)&L.h_p, cap * Np * 8, hipHostMallocDefault) != hipSuccess ||
+                  hipHostMalloc((void**)&L.h_int, cap * 3 * 4, hipHostMallocDefault) != hipSuccess))
+        rc = fail(RB_E_NOMEM, "rb_server_start: pinned host buffers");
+      if (rc) {
+        free_lanes(v.get());
+        return rc;
+      }
+    }
+    // packed operands of every basis size are built on first use; build the full one now
+    Pack* pk;
+    if (int rc = solve_pack_f64(c, s, s->N, &pk)) {
+      free_lanes(v.get());
+      return rc;
+    }
+  }
+  rb_server* raw = v.release();
+  raw->worker = std::thread(serve, raw);
+  *out = raw;
+  return RB_OK;
+}
+
+int rb_server_submit(rb_server* v, const rb_request* reqs, int n, long long* tickets) {
+  if (!v || (n > 0 && !reqs) || n < 0) return fail(RB_E_INVAL, "rb_server_submit: bad argument");
+  const auto now = Clock::now();
+  {
+    std::lock_guard<std::mutex> lk(v->qm);
+    if (v->stopping) return fail(RB_E_STATE, "rb_server_submit: server is stopping");
+    if (v->first_submit_s < 0 && n > 0)
+      v->first_submit_s = std::chrono::duration<double>(now - v->t0).count();
+    for (int i = 0; i < n; ++i) {
+      Pending q;
+      q.ticket = v->next_ticket++;
+      q.tag = reqs[i].tag;
+      q.N = reqs[i].N;
+      q.alpha = reqs[i].alpha;
+      q.re = reqs[i].re;
+      q.t_submit = now;
+      v->queue.push_back(q);
+      if (tickets) tickets[i] = q.ticket;
+    }
+    v->submitted += n;
+  }
+  v->qcv.notify_one();
+  return RB_OK;
+}
+
+int rb_server_poll(rb_server* v, rb_result* out, int max, int* n_out) {
+  if (!v || !n_out || (max > 0 && !out)) return fail(RB_E_INVAL, "rb_server_poll: bad argument");
+  std::lock_guard<std::mutex> lk(v->qm);
+  int n = 0;
+  while (n < max && !v->results.empty()) {
+    out[n++] = v->results.front();
+    v->results.pop_front();
+  }
+  *n_out = n;
+  return RB_OK;
+}
+
+int rb_server_stats(rb_server* v, rb_server_counters* st) {
+  if (!v || !st) return fail(RB_E_INVAL, "rb_server_stats: NULL argument");
+  std::lock_guard<std::mutex> lk(v->qm);
+  std::memset(st, 0, sizeof *st);
+  st->submitted = v->submitted;
+  st->completed = v->completed;
+  st->batches = v->batches;
+  if (!v->lat_ms.empty()) {
+    std::vector<double> l = v->lat_ms;
+    std::sort(l.begin(), l.end());
+    auto q = [&](double f) { return l[std::min(l.size() - 1, (size_t)(f * (l.size() - 1) + 0.5))]; };
+    st->p50_ms = q(0.50);
+    st->p99_ms = q(0.99);
+    st->max_ms = l.back();
+  }
+  st->mean_batch = v->batches ? (double)(v->completed) / v->batches : 0.0;
+  st->first_submit_s = v->first_submit_s;
+  st->last_done_s = v->last_done_s;
+  st->hbm_inflight_peak = v->inflight_peak;
+  std::snprintf(st->error, sizeof st->error, "%s", v->error.c_str());
+  return RB_OK;
+}
+
+int rb_server_stop(rb_server* v) {
+  if (!v) return fail(RB_E_INVAL, "rb_server_stop: NULL server");
+  {
+    std::lock_guard<std::mutex> lk(v->qm);
+    v->stopping = true;
+  }
+  v->qcv.notify_one();
+  if (v->worker.joinable()) v->worker.join();
+  {
+    std::lock_guard<std::mutex> ck(v->c->mu);
+    (void)hipSetDevice(v->c->device);
+    for (auto& L : v->lanes)
+      if (L.st) (void)hipStreamSynchronize(L.st);
+    free_lanes(v);
+  }
+  delete v;
   return RB_OK;
 }
 

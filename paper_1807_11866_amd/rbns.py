@@ -20,7 +20,10 @@ RB_PREC_F64, RB_PREC_F32, RB_PREC_BF16 = 0, 1, 2
 
 EXPORTED = ("rb_create", "rb_destroy", "rb_last_error", "rb_hbm_used", "rb_load_tensors",
             "rb_theta", "rb_solve_batch", "rb_solve_uneven", "rb_autotune", "rb_tuned_config",
-            "rb_recover_pressure", "rb_timing_enable", "rb_timing_read")
+            "rb_recover_pressure", "rb_server_start", "rb_server_submit", "rb_server_poll",
+            "rb_server_stats", "rb_server_stop", "rb_timing_enable", "rb_timing_read")
+RB_ST_FAILED = 5
+RB_MAX_N, RB_MAX_NP = 152, 64
 
 _dp = ct.POINTER(ct.c_double)
 _vp = ct.c_void_p
@@ -42,6 +45,32 @@ class TensorsDesc(ct.Structure):
 class SolveOpts(ct.Structure):
     _fields_ = [("tol", ct.c_double), ("max_iter", ct.c_int), ("precision", ct.c_int),
                 ("refine_steps", ct.c_int)]
+
+
+class ServerOpts(ct.Structure):
+    _fields_ = [("precision", ct.c_int), ("refine_steps", ct.c_int), ("max_iter", ct.c_int),
+                ("tol", ct.c_double), ("max_batch", ct.c_int), ("lanes", ct.c_int),
+                ("hbm_budget_bytes", ct.c_size_t), ("pressure", ct.c_int)]
+
+
+class Request(ct.Structure):
+    _fields_ = [("alpha", ct.c_double), ("re", ct.c_double), ("N", ct.c_int),
+                ("tag", ct.c_longlong)]
+
+
+class Result(ct.Structure):
+    _fields_ = [("ticket", ct.c_longlong), ("tag", ct.c_longlong), ("N", ct.c_int),
+                ("status", ct.c_int), ("iters", ct.c_int), ("pstatus", ct.c_int),
+                ("latency_ms", ct.c_double), ("u", ct.c_double * RB_MAX_N),
+                ("p", ct.c_double * RB_MAX_NP)]
+
+
+class ServerStats(ct.Structure):
+    _fields_ = [("submitted", ct.c_longlong), ("completed", ct.c_longlong),
+                ("batches", ct.c_longlong), ("p50_ms", ct.c_double), ("p99_ms", ct.c_double),
+                ("max_ms", ct.c_double), ("mean_batch", ct.c_double),
+                ("first_submit_s", ct.c_double), ("last_done_s", ct.c_double),
+                ("hbm_inflight_peak", ct.c_size_t), ("error", ct.c_char * 256)]
 
 
 _lib = None
@@ -73,6 +102,12 @@ def load(path=None):
     lib.rb_tuned_config.argtypes = [_vp, ct.c_int, ct.c_int, ct.c_int, ct.c_int,
                                     ct.POINTER(ct.c_int), ct.POINTER(ct.c_int)]
     lib.rb_recover_pressure.argtypes = ([_vp] + [ct.c_int] * 6 + [_vp] * 7 + [_vp])
+    lib.rb_server_start.argtypes = [_vp, ct.c_int, ct.POINTER(ServerOpts), ct.POINTER(_vp)]
+    lib.rb_server_submit.argtypes = [_vp, ct.POINTER(Request), ct.c_int,
+                                     ct.POINTER(ct.c_longlong)]
+    lib.rb_server_poll.argtypes = [_vp, ct.POINTER(Result), ct.c_int, ct.POINTER(ct.c_int)]
+    lib.rb_server_stats.argtypes = [_vp, ct.POINTER(ServerStats)]
+    lib.rb_server_stop.argtypes = [_vp]
     lib.rb_timing_enable.argtypes = [_vp, ct.c_int]
     lib.rb_timing_read.argtypes = [_vp, ct.c_char_p, ct.POINTER(ct.c_double),
                                    ct.POINTER(ct.c_int)]
@@ -287,3 +322,61 @@ class Solver:
         rb_recover_pressure(self.ctx, self.set, B, N, Np, u.shape[1], self.Np, th["ta"],
                             th["tc"], th["tf"], th["tb"], u, out["p"], out["pstatus"], stream)
         return out
+
+
+class Server:
+    """Continuous-batching server (rb_server_*) over a Solver's context and tensor set."""
+
+    def __init__(self, solver, precision=RB_PREC_F64, refine_steps=1, max_iter=10, tol=1e-12,
+                 max_batch=1024, lanes=3, hbm_budget_bytes=0, pressure=False):
+        self.solver = solver
+        o = ServerOpts(int(precision), int(refine_steps), int(max_iter), float(tol),
+                       int(max_batch), int(lanes), int(hbm_budget_bytes), int(bool(pressure)))
+        self.h = _vp()
+        _check(load().rb_server_start(solver.ctx, solver.set, ct.byref(o), ct.byref(self.h)))
+        self._buf = (Result * 4096)()
+
+    def submit(self, alpha, re, N, tags=None):
+        """Queue requests (arrays of equal length); returns their tickets (numpy int64)."""
+        import numpy as np
+        alpha = np.atleast_1d(np.asarray(alpha, dtype=np.float64))
+        n = alpha.shape[0]
+        re = np.broadcast_to(np.asarray(re, dtype=np.float64), (n,))
+        N = np.broadcast_to(np.asarray(N, dtype=np.int64), (n,))
+        tags = np.arange(n) if tags is None else np.broadcast_to(np.asarray(tags), (n,))
+        reqs = (Request * n)()
+        for i in range(n):
+            reqs[i].alpha, reqs[i].re, reqs[i].N, reqs[i].tag = (
+                float(alpha[i]), float(re[i]), int(N[i]), int(tags[i]))
+        tk = (ct.c_longlong * n)()
+        _check(load().rb_server_submit(self.h, reqs, n, tk))
+        return np.frombuffer(tk, dtype=np.int64).copy()
+
+    def poll(self):
+        """Finished results as a list of dicts (ticket, tag, N, status, iters, pstatus,
+        latency_ms, u, p)."""
+        import numpy as np
+        out = []
+        while True:
+            n = ct.c_int(0)
+            _check(load().rb_server_poll(self.h, self._buf, len(self._buf), ct.byref(n)))
+            for i in range(n.value):
+                r = self._buf[i]
+                out.append(dict(ticket=r.ticket, tag=r.tag, N=r.N, status=r.status,
+                                iters=r.iters, pstatus=r.pstatus, latency_ms=r.latency_ms,
+                                u=np.ctypeslib.as_array(r.u)[:r.N].copy(),
+                                p=np.ctypeslib.as_array(r.p).copy()))
+            if n.value < len(self._buf):
+                return out
+
+    def stats(self):
+        st = ServerStats()
+        _check(load().rb_server_stats(self.h, ct.byref(st)))
+        d = {k: getattr(st, k) for k, _ in ServerStats._fields_}
+        d["error"] = st.error.decode()
+        return d
+
+    def stop(self):
+        if self.h:
+            _check(load().rb_server_stop(self.h))
+            self.h = None
