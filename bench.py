@@ -46,6 +46,9 @@ def main():
     ap.add_argument("--plain", type=int, default=256,
                     help="requests timed on the plain B=1 path (0 = skip)")
     ap.add_argument("--check", type=int, default=64, help="requests re-solved by the oracle")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="after the bench, one plain device copy of this many MiB (the "
+                         "reference kernel for scaling HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -217,6 +220,14 @@ def main():
     }
     print(json.dumps(res), flush=True)
     s.close()
+    if args.copy_mib > 0:
+        n = args.copy_mib << 17                      # doubles
+        x = torch.ones(n, dtype=torch.float64, device=dev)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        log(f"[bench] copy reference: {args.copy_mib} MiB read + {args.copy_mib} MiB written")
 
 
 if __name__ == "__main__":

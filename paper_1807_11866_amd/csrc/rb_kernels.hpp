@@ -17,6 +17,8 @@
 //     converged drop out of the LU phase, and the workgroup exits when all have.
 #pragma once
 
+#include <type_traits>
+
 #include "rb_common.hpp"
 
 namespace rb {
@@ -102,6 +104,8 @@ struct NewtonState {
   int64_t mp;
   int NP;
   int nsplit;              // partial sums per request in Wv / the mixed-precision partials
+  int jslices;             // FP64 Jacobian slices (one per tensor chunk; 0: no FP64 J)
+  int64_t jstride;         // doubles between slices
 };
 
 struct NewtonF64Args {
@@ -155,22 +159,25 @@ static __global__ void newton_init_kernel(NewtonF64Args a) {
 // the mixed-precision refinement and the pressure right-hand side. Workgroup g handles the
 // 64-request tile g / nsplit and the row split g % nsplit (nsplit is a tuning knob, 8 by
 // default); with round-robin dispatch over the 8 XCDs and nsplit = 8 every workgroup of one
-// XCD reads the same eighth of the packed operand, which therefore stays in that XCD's L2. Wavefront w of the workgroup owns requests 16w..16w+15
-// of the tile and keeps its slice of W (the B operand) for one chunk of KC tensor k-steps in
-// registers, so the main loop touches no LDS; the four wavefronts walk the same row blocks
-// in the same order and share each A tile (one 512-byte line per k-step and row block)
-// through L1. Row blocks go four at a time: per k-step four A loads (issued kDepth k-steps
-// ahead; the loop over a chunk is unrolled at the compile-time length KC, so the pipeline is
-// static) feed four v_mfma_f64_16x16x4f64. The affine k-steps go first (chunk 0 only).
-// Tensor parts longer than 64 k-steps run as nchunk chunks; each chunk walks the row blocks
-// again with fresh accumulators, which the residual and pressure epilogues (linear in the
-// accumulator) fold chunk by chunk; for the Jacobian each chunk after the first adds its
-// accumulators to the stored J.
+// XCD reads the same eighth of the packed operand, which therefore stays in that XCD's L2.
+// Wavefront w of the workgroup owns requests 16w..16w+15 of the tile and keeps its slice of
+// W (the B operand: the affine k-steps and one chunk of at most kMaxKC tensor k-steps) in
+// registers, so the main loop touches no LDS; the four wavefronts walk the same row blocks in
+// the same order and share each A tile (one 512-byte line per k-step and row block) through
+// L1. Row blocks go four at a time; every k-step issues the four A loads kDepth k-steps ahead
+// and four v_mfma_f64_16x16x4f64. The k loop is unrolled at its compile-time length, and the
+// loads of the next group of row blocks are issued during the tail of the current one, so the
+// pipeline does not drain between groups. The affine part is padded to kAmax = 3 k-steps
+// (zero columns) so that every row block has the same static pipeline. Tensor parts longer
+// than 64 k-steps run as nchunk chunks, each walking the row blocks again with fresh
+// accumulators (the Jacobian adds each later chunk to what the earlier ones stored).
 //
 // Rows are m = j*R + i (R = N for the solve operand, R = Np for the pressure one). The
 // epilogue folds acc[m, b] * u_j(b) into per-row sums p_i(b) in LDS:
 //   Jacobian: the affine accumulator (A(mu) u; with J u the LU kernel forms
-//             F(u) = (J u + A u)/2 - f) and stores J;
+//             F(u) = (J u + A u)/2 - f); each 16x16 accumulator tile is transposed through
+//             a small per-wavefront LDS stage so that J goes out column-major per request
+//             (mp doubles per request) in 128-byte pieces;
 //   residual: affine accumulator with weight 1, tensor accumulators with weight 1/2, so
 //             p = A(mu) u + C(mu)(u,u)  (the tensor part applied to u is 2 C(u,u));
 //   pressure: every accumulator with weight 1, p = A_sv u + C_sv(u,u).
@@ -180,11 +187,12 @@ constexpr int kSplit = 8;      // default row splits, one per XCD
 constexpr int kMaxSplit = 16;  // largest split count (partial-sum buffers are sized for it)
 constexpr int kGroup = 4;      // row blocks per wavefront pass
 constexpr int kDepth = 4;      // k-steps of A operand in flight
-constexpr int kMaxKC = 64;     // longest tensor chunk held in registers
+constexpr int kMaxKC = 40;     // longest tensor chunk held in registers (no spills at 2 waves/SIMD)
+constexpr int kAmax = 3;       // affine k-steps of every packed row block (Q <= 12)
 
 struct ContractArgs {
-  const double* op;        // packed operand [nrb][nks][64]
-  int nrb, nks, kA;        // row blocks, k-steps per row block (kA + nchunk*KC), affine k-steps
+  const double* op;        // packed operand [nrb][nks][64], nks = kAmax + nchunk*KC
+  int nrb, nks, kA;        // row blocks, k-steps per row block, affine k-steps (= kAmax)
   int nchunk;              // tensor chunks of KC k-steps
   int nsplit;              // row splits per tile (1..kMaxSplit)
   int R, N, M;             // rows m = j*R + i, M = R*N
@@ -195,27 +203,30 @@ struct ContractArgs {
   const double* U;         // iterates, row b at U + b*ldU (rows >= B are not read)
   int ldU;
   const int* done;         // Newton flags [Bp] or nullptr
-  double* J;               // Jacobian store [Bp][mp] or nullptr
+  double* J;               // Jacobians [Bp][mp] per chunk slice, or nullptr
   int64_t mp;
+  int64_t jstride;         // doubles between the J slices of consecutive chunks
   double* part;            // partial row sums [nsplit][Bp][ldp]
   int ldp;
 };
 
-// LDS: the tile's iterates [kTile][N] and row sums [kTile][R].
-__host__ __device__ inline int64_t contract_lds_bytes(int N, int R) {
-  return 8 * (int64_t)kTile * (N + R);
+// LDS: the tile's iterates [kTile][N], row sums [kTile][R], theta^c [kTile][kMaxQc] and, for
+// the Jacobian, the transpose stage [kWaves][16][kStageLd].
+constexpr int kStageLd = 20;   // padded row of the stage (16-byte aligned, spreads banks)
+__host__ __device__ inline int64_t contract_lds_bytes(int N, int R, bool jac) {
+  return 8 * ((int64_t)kTile * (N + R + kMaxQc) + (jac ? kWaves * 16 * kStageLd : 0));
 }
 
 constexpr int kModeJac = 0, kModePressure = 1, kModeResid = 2;
 
 template <int kMode, int KC>
-__global__ __launch_bounds__(kThreads) void contract_f64_kernel(ContractArgs a) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void contract_f64_kernel(ContractArgs a) {
   extern __shared__ double smem[];
   const int N = a.N, R = a.R;
-  const int kA = a.kA;                     // affine k-steps (1..3)
-  constexpr int kAmax = 3;
   double* ul = smem;                       // [kTile][N]
   double* pl = ul + kTile * N;             // [kTile][R]
+  double* tcl = pl + kTile * R;            // [kTile][kMaxQc]
 
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int split = blockIdx.x % a.nsplit;
@@ -227,30 +238,32 @@ __global__ __launch_bounds__(kThreads) void contract_f64_kernel(ContractArgs a) 
     ul[idx] = bg < a.B ? a.U[(int64_t)bg * a.ldU + l] : 0.0;
   }
   for (int idx = tid; idx < kTile * R; idx += kThreads) pl[idx] = 0.0;
+  for (int idx = tid; idx < kTile * kMaxQc; idx += kThreads) {
+    const int b = idx / kMaxQc, q = idx - b * kMaxQc, bg = b0 + b;
+    tcl[idx] = (bg < a.B && q < a.Qc) ? a.tc[(int64_t)bg * a.Qc + q] : 0.0;
+  }
 
   // This lane's B-operand column: request bl = 16*wv + lane%16, k = ks*4 + lane/16.
-  // Affine rows k < 4*kA: theta^a_k; tensor row t = q*N + l: theta^c_q u_l.
+  // Affine rows k < 4*kAmax: theta^a_k (0 beyond Q); tensor row t = q*N + l: theta^c_q u_l.
   const int bl = 16 * wv + (lane & 15);
   const int bg = b0 + bl;
   const int k0 = lane >> 4;
-  double wA[kAmax], tcv[kMaxQc];
+  double wa[kAmax];
 #pragma unroll
   for (int ks = 0; ks < kAmax; ++ks) {
     const int k = ks * 4 + k0;
-    wA[ks] = (bg < a.B && k < a.Q) ? a.ta[(int64_t)bg * a.Q + k] : 0.0;
+    wa[ks] = (bg < a.B && k < a.Q) ? a.ta[(int64_t)bg * a.Q + k] : 0.0;
   }
-#pragma unroll
-  for (int q = 0; q < kMaxQc; ++q) tcv[q] = (bg < a.B && q < a.Qc) ? a.tc[(int64_t)bg * a.Qc + q] : 0.0;
   __syncthreads();
 
   const int rb_lo = (int)((int64_t)split * a.nrb / a.nsplit);
   const int rb_hi = (int)((int64_t)(split + 1) * a.nrb / a.nsplit);
   const int col = bl;                      // accumulator column (request) of this lane
-  const int nks = a.nks;
+  double* stg = tcl + kTile * kMaxQc + wv * 16 * kStageLd;   // this wavefront's stage
 
   // Accumulator layout of v_mfma_f64_16x16x4f64: lane l, element v = row l/16 + 4v,
-  // column l%16 of the 16x16 tile. fold(): w * acc[m] * u_j into p_i for m = j*R + i.
-  auto fold = [&](const f64x4 (&c)[kGroup], int g0, double w) {
+  // column l%16 of the 16x16 tile. fold(): wt * acc[m] * u_j into p_i for m = j*R + i.
+  auto fold = [&](const f64x4 (&c)[kGroup], int g0, double wt) {
     const int m0 = g0 * 16 + (lane >> 4);
     const int j0 = m0 / R, i0 = m0 - j0 * R;
 #pragma unroll
@@ -260,99 +273,102 @@ __global__ __launch_bounds__(kThreads) void contract_f64_kernel(ContractArgs a) 
         for (int v = 0; v < 4; ++v) {
           int i = i0 + 16 * r + 4 * v, j = j0;
           while (i >= R) { i -= R; ++j; }
-          if (j < N) atomicAdd(&pl[col * R + i], w * c[r][v] * ul[col * N + j]);
+          if (j < N) atomicAdd(&pl[col * R + i], wt * c[r][v] * ul[col * N + j]);
         }
       }
     }
   };
 
+  // One pass over this split's row blocks for the k-steps [k_first, k_first + NKS) of every
+  // packed row block, with W values w[0..NKS).
+  auto pass = [&](auto nks_c, const double* w, int k_first, int chunk) {
+    constexpr int NKS = decltype(nks_c)::value;
+    constexpr bool kAff = NKS == kAmax + KC;   // this pass starts with the affine k-steps
+    auto row_ptr = [&](int rb) {
+      return a.op + (int64_t)min(rb, rb_hi - 1) * a.nks * 64 + (int64_t)k_first * 64 + lane;
+    };
+    double x[NKS + kDepth][kGroup];
+#pragma unroll
+    for (int ks = 0; ks < kDepth; ++ks)
+#pragma unroll
+      for (int r = 0; r < kGroup; ++r) x[ks][r] = row_ptr(rb_lo + r)[ks * 64];
+    for (int g0 = rb_lo; g0 < rb_hi; g0 += kGroup) {
+      const double* cur[kGroup];
+      const double* nxt[kGroup];
+#pragma unroll
+      for (int r = 0; r < kGroup; ++r) {
+        cur[r] = row_ptr(g0 + r);
+        nxt[r] = row_ptr(g0 + kGroup + r);
+      }
+      f64x4 c[kGroup];
+#pragma unroll
+      for (int r = 0; r < kGroup; ++r) c[r] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int ks = 0; ks < NKS; ++ks) {
+        const int pf = ks + kDepth;
+#pragma unroll
+        for (int r = 0; r < kGroup; ++r)
+          x[pf][r] = pf < NKS ? cur[r][pf * 64] : nxt[r][(pf - NKS) * 64];
+#pragma unroll
+        for (int r = 0; r < kGroup; ++r)
+          c[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[ks][r], w[ks], c[r], 0, 0, 0);
+        if (kAff && ks == kAmax - 1 && kMode != kModePressure) {
+          fold(c, g0, 1.0);                // A(mu) u
+          if (kMode == kModeResid) {
+#pragma unroll
+            for (int r = 0; r < kGroup; ++r) c[r] = f64x4{0.0, 0.0, 0.0, 0.0};
+          }
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < kDepth; ++t)
+#pragma unroll
+        for (int r = 0; r < kGroup; ++r) x[t][r] = x[NKS + t][r];
+      if (kMode == kModeJac) {
+        // stage [request][row] -> lane l takes request l/4, rows 4*(l%4)..+3 of the block
+        const int q2 = lane >> 2, e0 = 4 * (lane & 3);
+#pragma unroll
+        for (int r = 0; r < kGroup; ++r) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) stg[(lane & 15) * kStageLd + (lane >> 4) + 4 * v] = c[r][v];
+          wave_lds_order();
+          const f64x4 val = *reinterpret_cast<const f64x4*>(&stg[q2 * kStageLd + e0]);
+          wave_lds_order();
+          if (g0 + r < rb_hi) {
+            f64x4* jp = reinterpret_cast<f64x4*>(a.J + chunk * a.jstride +
+                                                 (int64_t)(b0 + 16 * wv + q2) * a.mp +
+                                                 (g0 + r) * 16 + e0);
+            *jp = val;                     // cached: the LU kernel reads J next
+          }
+        }
+      } else {
+        fold(c, g0, kMode == kModeResid ? 0.5 : 1.0);
+      }
+    }
+  };
+
+  const double* ub = ul + bl * N;
+  const double* tcb = tcl + bl * kMaxQc;
   for (int ch = 0; ch < a.nchunk; ++ch) {
-    double wT[KC];
+    double w[kAmax + KC];
     {
       int t = ch * KC * 4 + k0, q = 0;
       while (t >= N && q < kMaxQc) { t -= N; ++q; }
       if (q >= kMaxQc) t = 0;              // padding k-steps: W = 0, any valid index
 #pragma unroll
       for (int ks = 0; ks < KC; ++ks) {
-        double tq = 0.0;
-#pragma unroll
-        for (int qq = 0; qq < kMaxQc; ++qq) tq = (q == qq) ? tcv[qq] : tq;
-        wT[ks] = tq * ul[bl * N + t];
+        w[kAmax + ks] = (q < kMaxQc ? tcb[q < kMaxQc ? q : 0] : 0.0) * ub[t];
         t += 4;
         while (t >= N && q < kMaxQc) { t -= N; ++q; }
         if (q >= kMaxQc) t = 0;
       }
     }
-    const int kt0 = kA + ch * KC;          // first k-step of this chunk
-
-    for (int g0 = rb_lo; g0 < rb_hi; g0 += kGroup) {
-      const double* opg[kGroup];
+    if (ch == 0) {
 #pragma unroll
-      for (int r = 0; r < kGroup; ++r)
-        opg[r] = a.op + (int64_t)min(g0 + r, rb_hi - 1) * nks * 64 + lane;
-      double x[KC][kGroup];
-#pragma unroll
-      for (int ks = 0; ks < kDepth && ks < KC; ++ks)
-#pragma unroll
-        for (int r = 0; r < kGroup; ++r) x[ks][r] = opg[r][(kt0 + ks) * 64];
-
-      f64x4 c[kGroup];
-#pragma unroll
-      for (int r = 0; r < kGroup; ++r) c[r] = f64x4{0.0, 0.0, 0.0, 0.0};
-      if (ch == 0) {
-        double xa[kAmax][kGroup];
-#pragma unroll
-        for (int ks = 0; ks < kAmax; ++ks)
-#pragma unroll
-          for (int r = 0; r < kGroup; ++r) xa[ks][r] = opg[r][min(ks, kA - 1) * 64];
-#pragma unroll
-        for (int ks = 0; ks < kAmax; ++ks) {
-          if (ks < kA) {
-#pragma unroll
-            for (int r = 0; r < kGroup; ++r)
-              c[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[ks][r], wA[ks], c[r], 0, 0, 0);
-          }
-        }
-        if (kMode != kModePressure) fold(c, g0, 1.0);     // A(mu) u
-        if (kMode == kModeResid) {
-#pragma unroll
-          for (int r = 0; r < kGroup; ++r) c[r] = f64x4{0.0, 0.0, 0.0, 0.0};
-        }
-      }
-
-#pragma unroll
-      for (int ks = 0; ks < KC; ++ks) {
-        if (ks + kDepth < KC) {
-#pragma unroll
-          for (int r = 0; r < kGroup; ++r) x[ks + kDepth][r] = opg[r][(kt0 + ks + kDepth) * 64];
-        }
-#pragma unroll
-        for (int r = 0; r < kGroup; ++r)
-          c[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[ks][r], wT[ks], c[r], 0, 0, 0);
-      }
-
-      if (kMode == kModeJac) {
-        // chunks after the first add to what the same lane stored before
-#pragma unroll
-        for (int r = 0; r < kGroup; ++r) {
-          if (g0 + r < rb_hi) {
-            double* jp = a.J + (int64_t)(b0 + col) * a.mp + (g0 + r) * 16 + (lane >> 4);
-            if (ch == 0) {
-              jp[0] = c[r][0];
-              jp[4] = c[r][1];
-              jp[8] = c[r][2];
-              jp[12] = c[r][3];
-            } else {
-              jp[0] += c[r][0];
-              jp[4] += c[r][1];
-              jp[8] += c[r][2];
-              jp[12] += c[r][3];
-            }
-          }
-        }
-      } else {
-        fold(c, g0, kMode == kModeResid ? 0.5 : 1.0);
-      }
+      for (int ks = 0; ks < kAmax; ++ks) w[ks] = wa[ks];
+      pass(std::integral_constant<int, kAmax + KC>{}, w, 0, 0);
+    } else {
+      pass(std::integral_constant<int, KC>{}, w + kAmax, kAmax + ch * KC, ch);
     }
   }
   __syncthreads();
@@ -378,9 +394,14 @@ __global__ __launch_bounds__(kThreads) void lu_f64_kernel(NewtonF64Args a, int i
   double ju = 0.0;
   bool bad = false;
 #pragma unroll
+  for (int c = 0; c < NP; ++c) r[c] = jb[(c < N ? c : N - 1) * N + lc];   // clamped: in bounds
+  for (int sl = 1; sl < a.s.jslices; ++sl) {               // further chunk slices of J
+#pragma unroll
+    for (int c = 0; c < NP; ++c) r[c] += jb[sl * a.s.jstride + (c < N ? c : N - 1) * N + lc];
+  }
+#pragma unroll
   for (int c = 0; c < NP; ++c) {
-    const double v = jb[(c < N ? c : N - 1) * N + lc];       // clamped: always in bounds
-    r[c] = (c < N && lane < N) ? v : (c == lane ? 1.0 : 0.0);
+    r[c] = (c < N && lane < N) ? r[c] : (c == lane ? 1.0 : 0.0);
     ju = fma(r[c], ub[c], ju);
     bad |= !finite_val(r[c]);
   }
@@ -436,6 +457,7 @@ __global__ __launch_bounds__(kWave * W) void lu_f64_mw_kernel(NewtonF64Args a, i
   if (a.s.done[b]) return;
   const int N = a.N;
   const double* jb = a.s.J + (int64_t)b * a.s.mp;
+  auto jload = [&](int sl, int c, int row) { return jb[sl * a.s.jstride + c * N + row]; };
   double* ub = a.s.U + (int64_t)b * NP;
   auto rhs_of = [&](int row, double ju) {
     double w = 0.0;
@@ -444,7 +466,8 @@ __global__ __launch_bounds__(kWave * W) void lu_f64_mw_kernel(NewtonF64Args a, i
     return -(0.5 * (ju + w) - a.s.Fv[(int64_t)b * NP + row]);
   };
   double nd2, nu2;
-  const int flag = mw_newton_update<double, NP, W>(jb, N, a.Nm, ub, a.H, rhs_of, sh, nd2, nu2);
+  const int flag = mw_newton_update<double, NP, W>(jload, a.s.jslices, N, a.Nm, ub, a.H, rhs_of,
+                                                   sh, nd2, nu2);
   if (threadIdx.x != 0) return;
   if (flag != 0) {
     a.s.status[b] = flag;

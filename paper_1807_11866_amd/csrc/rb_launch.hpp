@@ -11,7 +11,7 @@
 namespace rb {
 namespace launch {
 
-// FP64 contraction (chunk length (g.nks - g.kA) / g.nchunk: even, <= 64).
+// FP64 contraction (chunk length (g.nks - g.kA) / g.nchunk: even, <= kMaxKC).
 int contract_f64(int mode, const ContractArgs& g, hipStream_t st);
 // FP64 Newton LU: NP <= 64 one wavefront per system, NP > 64 (multiple of 8, <= 96) one
 // workgroup per system.

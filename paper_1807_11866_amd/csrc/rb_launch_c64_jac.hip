@@ -1,4 +1,4 @@
-// Instantiations of contract_f64_kernel<kModeJac, KT> for every even tensor chunk length KC <= 64.
+// Instantiations of contract_f64_kernel<kModeJac, KT> for every even tensor chunk length KC <= kMaxKC (40).
 #include "rb_launch.hpp"
 
 namespace rb {
@@ -6,7 +6,7 @@ namespace launch {
 
 template <int KT>
 static int go(const ContractArgs& g, hipStream_t st) {
-  const size_t lds = (size_t)contract_lds_bytes(g.N, g.R);
+  const size_t lds = (size_t)contract_lds_bytes(g.N, g.R, true);
   if (lds > 64 * 1024 &&
       hipFuncSetAttribute((const void*)contract_f64_kernel<kModeJac, KT>,
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
@@ -22,8 +22,7 @@ int contract_f64_jac(const ContractArgs& g, hipStream_t st) {
 #define RB_KT(n) case n: return go<n>(g, st);
     RB_KT(2) RB_KT(4) RB_KT(6) RB_KT(8) RB_KT(10) RB_KT(12) RB_KT(14) RB_KT(16) RB_KT(18)
     RB_KT(20) RB_KT(22) RB_KT(24) RB_KT(26) RB_KT(28) RB_KT(30) RB_KT(32) RB_KT(34) RB_KT(36)
-    RB_KT(38) RB_KT(40) RB_KT(42) RB_KT(44) RB_KT(46) RB_KT(48) RB_KT(50) RB_KT(52) RB_KT(54)
-    RB_KT(56) RB_KT(58) RB_KT(60) RB_KT(62) RB_KT(64)
+    RB_KT(38) RB_KT(40)
 #undef RB_KT
   }
   return -5;

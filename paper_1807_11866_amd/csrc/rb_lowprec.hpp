@@ -350,6 +350,8 @@ __global__ __launch_bounds__(kWave * W) void lu_lp_mw_kernel(LpNewtonArgs a, int
   if (a.s.done[b]) return;
   const int64_t Bp = a.s.Bp;
   const float* jb = a.J + (int64_t)b * a.mp;
+  const int N = a.N;
+  auto jload = [&](int, int c, int row) { return jb[c * N + row]; };
   double* ub = a.s.U + (int64_t)b * NP;
   auto rhs_of = [&](int row, float ju) {
     const double f = a.s.Fv[(int64_t)b * NP + row];
@@ -365,7 +367,8 @@ __global__ __launch_bounds__(kWave * W) void lu_lp_mw_kernel(LpNewtonArgs a, int
     return -(0.5 * (static_cast<double>(ju) + au) - f);
   };
   double nd2, nu2;
-  const int flag = mw_newton_update<float, NP, W>(jb, a.N, a.Nm, ub, a.H, rhs_of, sh, nd2, nu2);
+  const int flag = mw_newton_update<float, NP, W>(jload, 1, a.N, a.Nm, ub, a.H, rhs_of, sh, nd2,
+                                                  nu2);
   if (threadIdx.x != 0) return;
   if (flag != 0) {
     a.s.status[b] = flag;

@@ -166,7 +166,7 @@ int launch_grid(int64_t total) {
 // k-steps of a packed row block: affine part ceil(Q/4), tensor part ceil(Qc*N/4) split into
 // nchunk <= 64-k-step chunks of an even length KC (the FP64 contraction is instantiated per
 // even chunk length and holds one chunk of W in registers), zero padded.
-int affine_ksteps(int Q) { return (Q + 3) / 4; }
+int affine_ksteps(int) { return rb::kAmax; }   // padded: one static pipeline for every Q
 void tensor_chunks(int Qc, int N, int* nchunk, int* kc) {
   const int raw = (int)(ceil_to((int64_t)Qc * N, 4) / 4);
   *nchunk = (raw + rb::kMaxKC - 1) / rb::kMaxKC;
@@ -235,7 +235,7 @@ int solve_pack_lp(rb_ctx* c, Set* s, int N, bool bf16, Pack** out) {
   if (it != s->solve_lp.end()) { *out = &it->second; return RB_OK; }
   Pack p;
   p.nrb = (int)(ceil_to((int64_t)N * N, 16) / 16);
-  p.nks_s = bf16 ? 1 : affine_ksteps(s->Q);
+  p.nks_s = bf16 ? 1 : (s->Q + 3) / 4;
   p.nks = p.nks_s + lp_tensor_ksteps(s->Qc, N, bf16);
   const int64_t total = (int64_t)p.nrb * p.nks * 64 * (bf16 ? 8 : 1);
   int rc = dev_alloc(c, p.buf, total * (bf16 ? 2 : 4));
@@ -276,16 +276,17 @@ int workspace(rb_ctx* c, void* stream, size_t bytes, Workspace** out) {
 }
 
 // Carve the Newton state for Bp (padded) requests out of one workspace allocation.
-size_t newton_state_bytes(int64_t Bp, int NP, int64_t mp, int nsplit) {
-  return (size_t)(Bp * mp + (2 + nsplit) * Bp * NP + Bp) * sizeof(double) +
+size_t newton_state_bytes(int64_t Bp, int NP, int64_t mp, int nsplit, int jslices) {
+  return (size_t)(jslices * Bp * mp + (2 + nsplit) * Bp * NP + Bp) * sizeof(double) +
          (size_t)3 * Bp * sizeof(int) + 256;
 }
 
-rb::NewtonState carve_state(void* base, int64_t Bp, int NP, int64_t mp, int nsplit) {
+rb::NewtonState carve_state(void* base, int64_t Bp, int NP, int64_t mp, int nsplit,
+                            int jslices) {
   rb::NewtonState s;
   double* d = (double*)base;
   s.J = d;
-  d += Bp * mp;
+  d += jslices * Bp * mp;
   s.U = d;
   d += Bp * NP;
   s.Fv = d;
@@ -302,6 +303,8 @@ rb::NewtonState carve_state(void* base, int64_t Bp, int NP, int64_t mp, int nspl
   s.NP = NP;
   s.Bp = Bp;
   s.nsplit = nsplit;
+  s.jslices = jslices;
+  s.jstride = Bp * mp;
   return s;
 }
 
@@ -311,15 +314,28 @@ size_t lp_extra_bytes(int64_t Bp, int NP, int64_t mp, int nsplit) {
          (size_t)nsplit * Bp * NP * sizeof(double);
 }
 
-size_t solve_bytes(int64_t Bp, int NP, int64_t mp, int nsplit, int precision) {
-  size_t b = newton_state_bytes(Bp, NP, mp, nsplit);
-  if (precision != RB_PREC_F64) b += lp_extra_bytes(Bp, NP, mp, nsplit);
-  return (size_t)ceil_to((int64_t)b, 256);
+// FP64 Jacobian slices of a solve at basis size N: one per tensor chunk of the FP64 operand
+// (the mixed precisions keep their Jacobian in FP32 and need none).
+int jslices_for(const Set* s, int N, int precision) {
+  if (precision != RB_PREC_F64) return 0;
+  int n, kc;
+  tensor_chunks(s->Qc, N, &n, &kc);
+  return n;
 }
 
 // Register row length of the LU kernels: multiples of 4 up to 64 (one wavefront per system),
 // multiples of 8 beyond (one workgroup of ceil(NP/64) wavefronts per system).
 int np_bucket(int n) { return (int)ceil_to(n, n <= 64 ? 4 : 8); }
+
+// Workspace of one same-N batch (padded to Bp requests): Newton state plus, for the mixed
+// precisions, the low-precision buffers.
+size_t solve_bytes(const Set* s, int N, int64_t Bp, int nsplit, int precision) {
+  const int NP = np_bucket(N);
+  const int64_t mp = ceil_to((int64_t)N * N, 16);
+  size_t b = newton_state_bytes(Bp, NP, mp, nsplit, jslices_for(s, N, precision));
+  if (precision != RB_PREC_F64) b += lp_extra_bytes(Bp, NP, mp, nsplit);
+  return (size_t)ceil_to((int64_t)b, 256);
+}
 
 enum { FAM_JACOBIAN = 0, FAM_LU = 1, FAM_PRESSURE = 2, FAM_RESIDUAL = 3, FAM_COUNT = 4 };
 const char* const kFamilies[FAM_COUNT] = {"jacobian", "lu", "pressure", "residual"};
@@ -369,7 +385,7 @@ int enqueue_newton(rb_ctx* c, const rb::NewtonF64Args& a, bool lu_lds, hipStream
   g.ta = a.ta; g.tc = a.tc;
   g.U = a.s.U; g.ldU = NP;
   g.done = a.s.done;
-  g.J = a.s.J; g.mp = a.s.mp;
+  g.J = a.s.J; g.mp = a.s.mp; g.jstride = a.s.jstride;
   g.part = a.s.Wv; g.ldp = NP;
   hipLaunchKernelGGL(rb::newton_init_kernel, dim3(launch_grid(Bp * NP)), dim3(256), 0, st, a);
   for (int it = 0; it < a.maxit; ++it) {
@@ -420,7 +436,7 @@ int enqueue_newton_lp(rb_ctx* c, Set* s, const rb::NewtonF64Args& a, bool bf16, 
   gr.R = N; gr.N = N; gr.M = N * N;
   gr.Q = a.Q; gr.Qc = a.Qc; gr.B = a.B; gr.Bp = Bp;
   gr.ta = a.ta; gr.tc = a.tc; gr.U = a.s.U; gr.ldU = NP;
-  gr.done = a.s.done; gr.J = nullptr; gr.mp = 0;
+  gr.done = a.s.done; gr.J = nullptr; gr.mp = 0; gr.jstride = 0;
   gr.part = partA; gr.ldp = NP;
 
   rb::LpNewtonArgs la;
@@ -479,7 +495,7 @@ int enqueue_pressure(rb_ctx* c, Set* s, int B, int N, int Np, int ldu, int ldp,
   g.ta = ta; g.tc = tc;
   g.U = u; g.ldU = ldu;
   g.done = nullptr;
-  g.J = nullptr; g.mp = 0;
+  g.J = nullptr; g.mp = 0; g.jstride = 0;
   g.part = (double*)part; g.ldp = NPP; g.nsplit = rb::kSplit;
   rb::PressureF64Args a;
   a.Np = Np; a.Npm = s->Np; a.Qf = s->Qf; a.Qb = s->Qb; a.B = B; a.ldp = ldp; a.Bp = Bp;
@@ -536,14 +552,15 @@ rb::NewtonF64Args make_args(Set* s, Pack* pk, int N, int B, int ldu, const rb_so
   a.H = s->hasH ? (const double*)s->H.p : nullptr;
   a.u = u; a.iters = iters; a.status = status;
   const int64_t Bp = ceil_to(B, rb::kTile);
-  a.s = carve_state(region, Bp, np_bucket(N), ceil_to((int64_t)N * N, 16), nsplit);
+  a.s = carve_state(region, Bp, np_bucket(N), ceil_to((int64_t)N * N, 16), nsplit,
+                    jslices_for(s, N, o.precision));
   return a;
 }
 
 int enqueue_solve(rb_ctx* c, Set* s, const rb::NewtonF64Args& a, const rb_solve_opts& o,
                   const Tune& t, char* region, hipStream_t st) {
   if (o.precision == RB_PREC_F64) return enqueue_newton(c, a, t.lu_lds, st);
-  char* lp = region + newton_state_bytes(a.s.Bp, a.s.NP, a.s.mp, a.s.nsplit);
+  char* lp = region + newton_state_bytes(a.s.Bp, a.s.NP, a.s.mp, a.s.nsplit, a.s.jslices);
   return enqueue_newton_lp(c, s, a, o.precision == RB_PREC_BF16, o.refine_steps, lp, st);
 }
 
@@ -566,8 +583,8 @@ int autotune_batch(rb_ctx* c, Set* s, int set, rb::NewtonF64Args a, const rb_sol
     c->event_pool.push_back(e1);
     return rc;
   };
-  a.s = carve_state(region, Bp, NP, mp, rb::kMaxSplit);
-  char* lpb = region + newton_state_bytes(Bp, NP, mp, rb::kMaxSplit);
+  a.s = carve_state(region, Bp, NP, mp, rb::kMaxSplit, jslices_for(s, N, o.precision));
+  char* lpb = region + newton_state_bytes(Bp, NP, mp, rb::kMaxSplit, a.s.jslices);
   auto contract = [&](int nsplit) -> int {
     a.s.nsplit = nsplit;
     if (!lp) {
@@ -577,7 +594,7 @@ int autotune_batch(rb_ctx* c, Set* s, int set, rb::NewtonF64Args a, const rb_sol
       g.R = N; g.N = N; g.M = N * N;
       g.Q = a.Q; g.Qc = a.Qc; g.B = a.B; g.Bp = Bp;
       g.ta = a.ta; g.tc = a.tc; g.U = a.s.U; g.ldU = NP;
-      g.done = a.s.done; g.J = a.s.J; g.mp = mp;
+      g.done = a.s.done; g.J = a.s.J; g.mp = mp; g.jstride = a.s.jstride;
       g.part = a.s.Wv; g.ldp = NP;
       return launch_rc(rb::launch::contract_f64(rb::kModeJac, g, st), "autotune contraction");
     }
@@ -802,8 +819,7 @@ int rb_solve_batch(rb_ctx* c, int set, int B, int N, int ldu, const double* ta,
   const int64_t Bp = ceil_to(B, rb::kTile);
   const Tune t = tune_for(c, set, N, o.precision, Bp);
   Workspace* w;
-  if (int rc = workspace(c, stream, solve_bytes(Bp, np_bucket(N), ceil_to((int64_t)N * N, 16),
-                                                t.nsplit, o.precision), &w))
+  if (int rc = workspace(c, stream, solve_bytes(s, N, Bp, t.nsplit, o.precision), &w))
     return rc;
   char* region = (char*)w->buf.p;
   rb::NewtonF64Args a = make_args(s, pk, N, B, ldu, o, ta, tc, tf, fover, u0, u, iters, status,
@@ -829,8 +845,7 @@ int rb_autotune(rb_ctx* c, int set, int B, int N, const double* ta, const double
   if (int rc = solve_pack_f64(c, s, N, &pk)) return rc;
   const int64_t Bp = ceil_to(B, rb::kTile);
   Workspace* w;
-  if (int rc = workspace(c, stream, solve_bytes(Bp, np_bucket(N), ceil_to((int64_t)N * N, 16),
-                                                rb::kMaxSplit, o.precision), &w))
+  if (int rc = workspace(c, stream, solve_bytes(s, N, Bp, rb::kMaxSplit, o.precision), &w))
     return rc;
   char* region = (char*)w->buf.p;
   rb::NewtonF64Args a = make_args(s, pk, N, B, N, o, ta, tc, tf, nullptr, nullptr, nullptr,
@@ -919,8 +934,7 @@ int rb_solve_uneven(rb_ctx* c, int set, int B, const int* Nd, int ldu, const dou
   const size_t o_u0 = take(u0 ? Bs * Nm * 8 : 8), o_u = take(Bs * Nm * 8);
   const size_t o_it = take(Bs * 4), o_st = take(Bs * 4), o_perm = take((Bs + nbad) * 4);
   for (auto& g : gs)
-    g.region = take(solve_bytes(g.Bp, np_bucket(g.N), ceil_to((int64_t)g.N * g.N, 16),
-                                rb::kMaxSplit, o.precision));
+    g.region = take(solve_bytes(s, g.N, g.Bp, rb::kMaxSplit, o.precision));
   Workspace* w;
   if (int rc = workspace(c, stream, off, &w)) return rc;
   char* base = (char*)w->buf.p;
@@ -1185,7 +1199,7 @@ size_t batch_bytes(rb_server* v, const std::vector<std::pair<int, int>>& groups)
     const int N = g.first;
     const int64_t Bp = ceil_to(g.second, rb::kTile);
     const Tune t = tune_for(v->c, v->set, N, v->o.precision, Bp);
-    b += solve_bytes(Bp, np_bucket(N), ceil_to((int64_t)N * N, 16), t.nsplit, v->o.precision);
+    b += solve_bytes(v->s, N, Bp, t.nsplit, v->o.precision);
     if (v->o.pressure) b += (size_t)ceil_to((int64_t)pressure_bytes(g.second, v->s->Np), 256);
   }
   return b;
@@ -1239,7 +1253,7 @@ int launch_batch(rb_server* v, Lane& L) {
                   tf + (int64_t)r0 * s->Qf, nullptr, nullptr, u + (int64_t)r0 * Nm, it + r0,
                   stt + r0, base, t.nsplit);
     if (int rc = enqueue_solve(c, s, a, o, t, base, L.st)) return rc;
-    base += solve_bytes(Bp, np_bucket(N), ceil_to((int64_t)N * N, 16), t.nsplit, o.precision);
+    base += solve_bytes(s, N, Bp, t.nsplit, o.precision);
     if (v->o.pressure) {
       if (int rc = enqueue_pressure(c, s, n, N, Np, Nm, Np, ta + (int64_t)r0 * s->Q,
                                     tc + (int64_t)r0 * s->Qc, tf + (int64_t)r0 * s->Qf,
