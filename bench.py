@@ -7,12 +7,18 @@ MFMA, pivoted LU, update, stopping test) and the a posteriori pressure recovery.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload batched_n50]
 
-Prints one JSON line (see the keys below). Progress goes to stderr.
+Besides the batched FP64 headline (`value`), the JSON line carries, on the same N = 50
+tensor set and parameters: the plain per-solve GPU path (the same library, one request per
+call), the mixed-precision batched path (BF16 tensors on MFMA + FP64-residual refinement),
+and the continuous-batching server under Poisson arrivals (throughput, p50/p99 latency);
+each with its maximum relative error against the FP64 oracle on a checked sample.
+Progress goes to stderr.
 """
 
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -30,9 +36,41 @@ PEAK = {  # MI355X published dense peaks
     "hbm_gbs": 8000.0,
 }
 
+# Sources whose change invalidates the HBM byte counts recorded under profiles/.
+TRAFFIC_SOURCES = ("paper_1807_11866_amd/csrc/rb_kernels.hpp",
+                   "paper_1807_11866_amd/csrc/rb_common.hpp")
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def sources_digest():
+    h = hashlib.sha256()
+    for p in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(kernel):
+    """HBM bytes per launch of `kernel` from profiles/traffic.json, if recorded for the
+    current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("sources_digest") != sources_digest():
+        return None
+    k = t.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("hbm_bytes_per_launch")
+
+
+def rel_err(a, b):
+    nb = np.linalg.norm(b, axis=-1)
+    return np.linalg.norm(a - b, axis=-1) / np.where(nb > 0, nb, 1.0)
 
 
 def main():
@@ -44,8 +82,13 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--plain", type=int, default=256,
-                    help="requests timed on the plain B=1 path (0 = skip)")
+                    help="requests timed on the plain one-request-per-call path (0 = skip)")
     ap.add_argument("--check", type=int, default=64, help="requests re-solved by the oracle")
+    ap.add_argument("--mixed-refine", type=int, default=3,
+                    help="refinement steps of the BF16 mixed-precision leg (-1 = skip)")
+    ap.add_argument("--serve-rates", default="200000,1000000",
+                    help="Poisson arrival rates (req/s) of the serving leg ('' = skip)")
+    ap.add_argument("--serve-seconds", type=float, default=1.5)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the bench, one plain device copy of this many MiB (the "
                          "reference kernel for scaling HBM byte counters)")
@@ -54,12 +97,13 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         log("bench.py: only --gpus 1 is supported (the solves are independent per parameter;"
-            " see DESIGN.md for how the path would shard)")
+            " DESIGN.md describes how the path would shard)")
         sys.exit(2)
 
     import torch
     from paper_1807_11866_amd import rbns
     from rbinputs import get_config, make_tensor_set, draw_mu
+    from rbinputs.synth import draw_arrivals
 
     cfg = get_config(args.workload)
     log(f"[bench] generating tensors for {args.workload}")
@@ -107,50 +151,57 @@ def main():
     status = out["status"].cpu().numpy()
     pstatus = pout["pstatus"].cpu().numpy()
 
-    # ---- roofline of the dominant kernel (algorithmic flops / live HIP-event durations) ----
+    # ---- rooflines (algorithmic flops / live HIP-event durations of each family) ----------
+    # unit = one (request, Newton update); launches of a family include the ones in which
+    # every request had already converged (they exit at once).
     K = ts.Q + ts.Qc * N
-    jac_flops_unit = 2.0 * N * N * K                     # per (request, Newton iteration)
-    lu_flops_unit = 2.0 / 3.0 * N ** 3 + 2.0 * N * N * 2  # LU + triangular solves + J u
     units = float(iters.sum()) * args.steps
-    jac_ms, jac_n = fams["jacobian"]
-    lu_ms, lu_n = fams["lu"]
-    pr_ms, pr_n = fams["pressure"]
+    per_unit = {
+        "jacobian": 2.0 * N * N * K,                        # J (and A u) contraction
+        "lu": 2.0 / 3.0 * N ** 3 + 2.0 * N * N * 2,         # LU + triangular solves + J u
+    }
+    pflops = 2.0 * Np * N * K + 2.0 / 3.0 * Np ** 3 + 2.0 * Np * Np * 2
+    kern = {}
+    for f, (ms, n) in fams.items():
+        work = per_unit[f] * units if f in per_unit else pflops * B * args.steps
+        kern[f] = dict(total_ms=ms, launches=n, avg_launch_ms=(ms / n if n else None),
+                       achieved_tflops=work / (ms * 1e-3) / 1e12 if ms > 0 else None)
+    names = {"jacobian": ("contract_f64_kernel<kModeJac> (MFMA-F64 Jacobian + A(mu)u)", "mfma",
+                          PEAK["fp64_mfma_tflops"]),
+             "lu": ("lu_f64_kernel (FP64 register LU + update)", "alu",
+                    PEAK["fp64_vector_tflops"]),
+             "pressure": ("contract_f64_kernel<kModePressure> + plu_f64_kernel", "mfma",
+                          PEAK["fp64_mfma_tflops"])}
+    for f in kern:
+        kern[f]["kernel"], kern[f]["bound"], kern[f]["peak_tflops"] = names[f]
+        a = kern[f]["achieved_tflops"]
+        kern[f]["frac"] = a / names[f][2] if a else None
     dominant = max(fams, key=lambda f: fams[f][0])
-    if dominant == "jacobian":
-        achieved = units * jac_flops_unit / (jac_ms * 1e-3) / 1e12
-        roof = dict(bound="mfma", achieved=achieved, peak=PEAK["fp64_mfma_tflops"],
-                    unit="TFLOP/s", kernel="jac_f64_kernel (MFMA-F64 Jacobian + residual)")
-    elif dominant == "lu":
-        achieved = units * lu_flops_unit / (lu_ms * 1e-3) / 1e12
-        roof = dict(bound="alu", achieved=achieved, peak=PEAK["fp64_vector_tflops"],
-                    unit="TFLOP/s", kernel="lu_f64_kernel (FP64 VALU pivoted LU)")
-    else:
-        pflops = 2.0 * Np * N * K + 2.0 / 3.0 * Np ** 3
-        achieved = B * args.steps * pflops / (pr_ms * 1e-3) / 1e12
-        roof = dict(bound="mfma", achieved=achieved, peak=PEAK["fp64_mfma_tflops"],
-                    unit="TFLOP/s", kernel="pressure_f64_kernel")
-    roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
-    roof["avg_launch_ms"] = {f: (fams[f][0] / fams[f][1] if fams[f][1] else None) for f in fams}
-    roof["launches"] = {f: fams[f][1] for f in fams}
-    roof["total_ms"] = {f: fams[f][0] for f in fams}
+    d = kern[dominant]
+    roof = dict(bound=d["bound"], achieved=d["achieved_tflops"], peak=d["peak_tflops"],
+                unit="TFLOP/s", frac=d["frac"], kernel=d["kernel"],
+                avg_launch_ms=d["avg_launch_ms"],
+                units_per_launch=(units / d["launches"] if dominant != "pressure" else B),
+                work_per_unit_flop=(per_unit.get(dominant, pflops)))
+    roof["traffic"] = recorded_traffic(dominant)
+    roof["jacobian_contraction"] = kern["jacobian"]
+    roof["kernels"] = kern
 
-    # ---- parity of the timed outputs against the oracle on a sample ----
+    # ---- parity of the timed outputs against the oracle on a sample ------------------------
     extra = {}
+    idx = np.linspace(0, B - 1, max(args.check, 1)).astype(int)
+    ref = None
     if args.check > 0:
-        import oracle
-        idx = np.linspace(0, B - 1, args.check).astype(int)
-        r = oracle.solve_batch(oracle.OracleSet(ts), mu_h[idx], pressure_np=Np,
-                               tol=cfg["tol"], maxit=cfg["max_iter"])
+        import oracle  # CPU reference (test infrastructure)
+        ref = oracle.solve_batch(oracle.OracleSet(ts), mu_h[idx], pressure_np=Np,
+                                 tol=cfg["tol"], maxit=cfg["max_iter"])
         u = out["u"].cpu().numpy()[idx]
         p = pout["p"].cpu().numpy()[idx]
-        eu = np.linalg.norm(u - r["u"], axis=1) / np.linalg.norm(r["u"], axis=1)
-        ep = np.linalg.norm(p - r["p"], axis=1) / np.linalg.norm(r["p"], axis=1)
-        extra["max_rel_err_u"] = float(eu.max())
-        extra["max_rel_err_p"] = float(ep.max())
+        extra["max_rel_err_u"] = float(rel_err(u, ref["u"]).max())
+        extra["max_rel_err_p"] = float(rel_err(p, ref["p"]).max())
         extra["checked_requests"] = int(len(idx))
 
-    # ---- plain per-solve GPU path: the same library, B = 1 sequential calls ----
+    # ---- plain per-solve GPU path: the same library, one request per call ------------------
     if args.plain > 0:
         P = min(args.plain, B)
         th1 = {k: v[:1].clone() for k, v in th.items()}
@@ -170,15 +221,108 @@ def main():
             s.pressure(th1, o1["u"], out=p1, stream=stream)
             torch.cuda.synchronize()
         tp1 = time.perf_counter()
-        extra["plain_value"] = P / (tp1 - tp0)
-        extra["plain_requests"] = P
-        extra["speedup_vs_plain"] = value / extra["plain_value"]
-        log(f"[bench] plain B=1 path: {extra['plain_value']:.4g} solves/s")
+        extra["plain"] = dict(value=P / (tp1 - tp0), unit="solves/s", requests=P,
+                              mean_ms=1e3 * (tp1 - tp0) / P)
+        extra["speedup_batched_vs_plain"] = value / extra["plain"]["value"]
+        log(f"[bench] plain path: {extra['plain']['value']:.4g} solves/s")
 
-    # ---- CPU baseline: the oracle as it stands, bounded sample of the same workload ----
+    # ---- mixed precision: BF16 tensors on MFMA, FP32 LU, FP64-residual refinement ----------
+    if args.mixed_refine >= 0:
+        mo = dict(u=torch.empty(B, N, **f64), iters=torch.empty(B, dtype=torch.int32, device=dev),
+                  status=torch.empty(B, dtype=torch.int32, device=dev))
+
+        def mstep():
+            rbns.rb_theta(s.ctx, s.set, B, mu, th["ta"], th["tc"], th["tf"], th["tb"], stream)
+            s.solve(th, out=mo, tol=cfg["tol"], max_iter=cfg["max_iter"],
+                    precision=rbns.RB_PREC_BF16, refine_steps=args.mixed_refine, stream=stream)
+            s.pressure(th, mo["u"], out=pout, stream=stream)
+        for _ in range(2):
+            mstep()
+        torch.cuda.synchronize()
+        nm = max(3, args.steps // 2)
+        tm0 = time.perf_counter()
+        for _ in range(nm):
+            mstep()
+        torch.cuda.synchronize()
+        tm1 = time.perf_counter()
+        mix = dict(value=B * nm / (tm1 - tm0), unit="solves/s", refine_steps=args.mixed_refine,
+                   dtype="bf16 tensors / fp32 accumulate + lu / fp64 residual and iterate",
+                   status_hist=np.bincount(mo["status"].cpu().numpy(), minlength=5).tolist())
+        if ref is not None:
+            mix["max_rel_err_u"] = float(rel_err(mo["u"].cpu().numpy()[idx], ref["u"]).max())
+            mix["max_rel_err_p"] = float(rel_err(pout["p"].cpu().numpy()[idx], ref["p"]).max())
+        extra["mixed_bf16"] = mix
+        log(f"[bench] mixed BF16 + {args.mixed_refine} refinement steps: {mix['value']:.4g} solves/s")
+
+    # ---- served: continuous batching under Poisson arrivals --------------------------------
+    rates = [float(r) for r in args.serve_rates.split(",") if r.strip()]
+    if rates:
+        served = {}
+        srv = rbns.Server(s, precision=rbns.RB_PREC_F64, max_iter=cfg["max_iter"],
+                          tol=cfg["tol"], max_batch=4096, lanes=3, pressure=True)
+        try:
+            srv.submit(mu_h[:256, 0], mu_h[:256, 1], N)      # warm the lanes
+            got = 0
+            while got < 256:
+                got += len(srv.poll_array())
+                time.sleep(1e-4)
+            pos = {int(b): k for k, b in enumerate(idx)}
+            for rate in rates:
+                arr = draw_arrivals(cfg, rate, args.serve_seconds)
+                n = len(arr)
+                sel = np.arange(n) % B
+                st0 = srv.stats()
+                lat = np.full(n, np.nan)
+                stat = np.full(n, -1, dtype=np.int64)
+                chk = [k for k in range(n) if int(sel[k]) in pos][:len(idx)]
+                chk_set = {k: m for m, k in enumerate(chk)}
+                cu = np.zeros((len(chk), N))
+                cp = np.zeros((len(chk), Np))
+                got = 0
+                i = 0
+                t0s = time.perf_counter()
+                while i < n or got < n:
+                    now = time.perf_counter() - t0s
+                    j = int(np.searchsorted(arr, now, side="right"))
+                    if j > i:
+                        srv.submit(mu_h[sel[i:j], 0], mu_h[sel[i:j], 1], N, tags=np.arange(i, j))
+                        i = j
+                    ra = srv.poll_array()
+                    if len(ra):
+                        tg = ra["tag"]
+                        lat[tg] = ra["latency_ms"]
+                        stat[tg] = ra["status"]
+                        got += len(ra)
+                        for r in ra:
+                            m = chk_set.get(int(r["tag"]))
+                            if m is not None:
+                                cu[m] = r["u"][:N]
+                                cp[m] = r["p"][:Np]
+                    elif i >= n:
+                        time.sleep(2e-5)
+                t1s = time.perf_counter()
+                st1 = srv.stats()
+                ent = dict(offered_req_s=rate, requests=n, value=n / (t1s - t0s),
+                           unit="solves/s", p50_ms=float(np.percentile(lat, 50)),
+                           p99_ms=float(np.percentile(lat, 99)), max_ms=float(lat.max()),
+                           batches=int(st1["batches"] - st0["batches"]),
+                           status_hist=np.bincount(stat, minlength=6).tolist())
+                ent["mean_batch"] = n / max(ent["batches"], 1)
+                if ref is not None and chk:
+                    rr = np.array([pos[int(sel[k])] for k in chk])
+                    ent["max_rel_err_u"] = float(rel_err(cu, ref["u"][rr]).max())
+                    ent["max_rel_err_p"] = float(rel_err(cp, ref["p"][rr]).max())
+                served[f"{int(rate)}"] = ent
+                log(f"[bench] served at {rate:.3g} req/s: {ent['value']:.4g} solves/s, "
+                    f"p50 {ent['p50_ms']:.3f} ms, p99 {ent['p99_ms']:.3f} ms")
+        finally:
+            srv.stop()
+        extra["served"] = served
+
+    # ---- CPU baseline: the oracle as it stands, bounded sample of the same workload --------
     cpu = None
     if not args.no_cpu:
-        import oracle
+        import oracle  # CPU reference (test infrastructure)
         oset = oracle.OracleSet(ts)
         done, tc0 = 0, time.perf_counter()
         threads = 0

@@ -1467,11 +1467,23 @@ int rb_server_start(rb_ctx* c, int set, const rb_server_opts* opts, rb_server** 
         return rc;
       }
     }
-    // packed operands of every basis size are built on first use; build the full one now
+    // packed operands of every basis size are built on first use; build the full one now,
+    // and size each lane's workspace for a full batch at the largest basis size, so that
+    // batches do not wait for a workspace to grow
     Pack* pk;
     if (int rc = solve_pack_f64(c, s, s->N, &pk)) {
       free_lanes(v.get());
       return rc;
+    }
+    const size_t ws = batch_bytes(v.get(), {{s->N, v->cap}});
+    if (!o.hbm_budget_bytes || ws <= o.hbm_budget_bytes) {
+      for (auto& L : v->lanes) {
+        Workspace* w;
+        if (int rc = workspace(c, L.st, ws, &w)) {
+          free_lanes(v.get());
+          return rc;
+        }
+      }
     }
   }
   rb_server* raw = v.release();

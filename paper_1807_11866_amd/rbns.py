@@ -336,38 +336,60 @@ class Server:
         _check(load().rb_server_start(solver.ctx, solver.set, ct.byref(o), ct.byref(self.h)))
         self._buf = (Result * 4096)()
 
+    _REQ = None
+
+    @classmethod
+    def _req_dtype(cls):
+        import numpy as np
+        if cls._REQ is None:
+            cls._REQ = np.dtype({"names": ["alpha", "re", "N", "tag"],
+                                 "formats": ["<f8", "<f8", "<i4", "<i8"],
+                                 "offsets": [Request.alpha.offset, Request.re.offset,
+                                             Request.N.offset, Request.tag.offset],
+                                 "itemsize": ct.sizeof(Request)})
+        return cls._REQ
+
     def submit(self, alpha, re, N, tags=None):
-        """Queue requests (arrays of equal length); returns their tickets (numpy int64)."""
+        """Queue requests (arrays of equal length, or scalars broadcast); returns their
+        tickets (numpy int64)."""
         import numpy as np
         alpha = np.atleast_1d(np.asarray(alpha, dtype=np.float64))
         n = alpha.shape[0]
-        re = np.broadcast_to(np.asarray(re, dtype=np.float64), (n,))
-        N = np.broadcast_to(np.asarray(N, dtype=np.int64), (n,))
-        tags = np.arange(n) if tags is None else np.broadcast_to(np.asarray(tags), (n,))
-        reqs = (Request * n)()
-        for i in range(n):
-            reqs[i].alpha, reqs[i].re, reqs[i].N, reqs[i].tag = (
-                float(alpha[i]), float(re[i]), int(N[i]), int(tags[i]))
-        tk = (ct.c_longlong * n)()
-        _check(load().rb_server_submit(self.h, reqs, n, tk))
-        return np.frombuffer(tk, dtype=np.int64).copy()
+        reqs = np.zeros(n, dtype=self._req_dtype())
+        reqs["alpha"] = alpha
+        reqs["re"] = np.broadcast_to(np.asarray(re, dtype=np.float64), (n,))
+        reqs["N"] = np.broadcast_to(np.asarray(N, dtype=np.int32), (n,))
+        reqs["tag"] = np.arange(n) if tags is None else np.broadcast_to(np.asarray(tags), (n,))
+        tk = np.empty(n, dtype=np.int64)
+        _check(load().rb_server_submit(self.h, reqs.ctypes.data_as(ct.POINTER(Request)), n,
+                                       tk.ctypes.data_as(ct.POINTER(ct.c_longlong))))
+        return tk
 
-    def poll(self):
-        """Finished results as a list of dicts (ticket, tag, N, status, iters, pstatus,
-        latency_ms, u, p)."""
+    def poll_array(self):
+        """Finished results as a numpy structured array with the fields of rb_result."""
         import numpy as np
-        out = []
+        parts = []
         while True:
             n = ct.c_int(0)
             _check(load().rb_server_poll(self.h, self._buf, len(self._buf), ct.byref(n)))
-            for i in range(n.value):
-                r = self._buf[i]
-                out.append(dict(ticket=r.ticket, tag=r.tag, N=r.N, status=r.status,
-                                iters=r.iters, pstatus=r.pstatus, latency_ms=r.latency_ms,
-                                u=np.ctypeslib.as_array(r.u)[:r.N].copy(),
-                                p=np.ctypeslib.as_array(r.p).copy()))
+            if n.value:
+                parts.append(np.ctypeslib.as_array(self._buf)[:n.value].copy())
             if n.value < len(self._buf):
-                return out
+                break
+        if not parts:
+            return np.ctypeslib.as_array(self._buf)[:0].copy()
+        return np.concatenate(parts)
+
+    def poll(self):
+        """Finished results as a list of dicts (ticket, tag, N, status, iters, pstatus,
+        latency_ms, u (first N entries), p)."""
+        out = []
+        for r in self.poll_array():
+            out.append(dict(ticket=int(r["ticket"]), tag=int(r["tag"]), N=int(r["N"]),
+                            status=int(r["status"]), iters=int(r["iters"]),
+                            pstatus=int(r["pstatus"]), latency_ms=float(r["latency_ms"]),
+                            u=r["u"][:int(r["N"])].copy(), p=r["p"].copy()))
+        return out
 
     def stats(self):
         st = ServerStats()
