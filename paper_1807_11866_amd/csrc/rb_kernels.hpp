@@ -1,20 +1,19 @@
-// rb_kernels.hpp -- gfx950 kernels of the online reduced Navier-Stokes solver.
+// rb_kernels.hpp -- gfx950 kernels of the online reduced Navier-Stokes solver (FP64 path).
 //
-// Work decomposition (a workgroup tile = 32 requests that share a basis size N):
-//   * Jacobian + affine contraction on MFMA (paper Section 3.5 / 3.4): for the BT requests
-//       J[(i,j), b] = sum_k Op[(i,j), k] W[k, b],  Op = [ S_flat | A_flat ],
-//       S_q[i,j,l] = C_q[i,j,l] + C_q[i,l,j],  W = [ theta^c_q(b) u_l(b) ; theta^a_q(b) ],
-//     i.e. one GEMM of shape (N^2) x (Qc N + Q) x BT per Newton step, with the operand
-//     tiles pre-packed in MFMA order so every wave load is a contiguous 512-byte line.
-//     W lives in LDS; Op streams from L2/HBM once per workgroup per step.
-//   * Residual in the GEMM epilogue: after the S part the accumulator holds J_c = C(.,u) +
-//     C(u,.), whose product with u is 2 C(u,u); the epilogue folds J_c[i,j] u_j into an LDS
-//     vector w, so F(u) = J u - w/2 - f needs no second pass over the tensors.
-//   * Pivoted LU in registers: one wavefront per system, one row per lane, pivot search by
-//     a wavefront argmax, pivot-row broadcast by readlane; the update is applied and the
-//     stopping test (norm given by the Gram matrix H) evaluated in the same wavefront.
-//   * The whole Newton loop of the workgroup runs inside one launch; requests that have
-//     converged drop out of the LU phase, and the workgroup exits when all have.
+// One Newton step of a batch of same-N requests is two launches (Sections 3.4, 3.5):
+//   * contract_f64_kernel: the Jacobian and affine contraction on MFMA,
+//       J[(j,i), b] = sum_k Op[(j,i), k] W[k, b],  Op = [ A_flat | S_flat ],
+//       S_q[i,j,l] = C_q[i,j,l] + C_q[i,l,j],  W = [ theta^a_q(b) ; theta^c_q(b) u_l(b) ],
+//     one GEMM of shape N^2 x (Q + Qc N) x B per step, the operand pre-packed in MFMA order
+//     so that every wavefront load is one contiguous 512-byte line; its epilogue also folds
+//     the affine accumulator with u into A(mu) u, from which the LU kernel forms the residual
+//     F(u) = (J u + A(mu) u)/2 - f without a second pass over the tensors (J u = A u + 2
+//     C(u,u) for the symmetrised tensor part). The same kernel, with other epilogues, gives
+//     the FP64 residual of the mixed-precision refinement and the pressure right-hand side.
+//   * lu_f64_kernel: one wavefront per request, one row per lane in registers, partial
+//     pivoting (wavefront argmax), pivot-row broadcast by readlane, update of the FP64
+//     iterate and the stopping test; lu_f64_mw_kernel spreads larger systems over a workgroup.
+// Requests that have converged are skipped by both kernels through per-request flags.
 #pragma once
 
 #include <type_traits>
