@@ -73,6 +73,198 @@ def rel_err(a, b):
     return np.linalg.norm(a - b, axis=-1) / np.where(nb > 0, nb, 1.0)
 
 
+def other_workload(args):
+    """The other synthetic workloads, each timed the same way (inputs resident, HIP-event
+    kernel timing, oracle check on a sample):
+      single_n10      the plain single solve (B = 1 per call, FP64)
+      mixed_n100      B = 32768 at N = 100: BF16 tensors, FP32 LU, FP64-residual refinement
+      uneven_n20_100  B = 16384 with N in {20,...,100} in one call (FP32 + refinement)
+      serve_n150      the server under Poisson arrivals, N ~ U{20..150}, FP32 + refinement
+    """
+    import torch
+    from paper_1807_11866_amd import rbns
+    from rbinputs import get_config, make_tensor_set, draw_mu, draw_basis_sizes
+    from rbinputs.synth import draw_arrivals
+    import oracle  # CPU reference (test infrastructure)
+
+    name = args.workload
+    cfg = get_config(name)
+    log(f"[bench] generating tensors for {name}")
+    ts = make_tensor_set(cfg)
+    dev = torch.device("cuda", 0)
+    f64 = dict(dtype=torch.float64, device=dev)
+    s = rbns.Solver(ts, device=0)
+    stream = torch.cuda.current_stream()
+    extra, roof, dtype = {}, None, "f64"
+    B = cfg.get("B", 1)
+    mu_h = draw_mu(cfg, B)
+    mu = torch.as_tensor(mu_h, device=dev)
+    th = s.theta(mu)
+    torch.cuda.synchronize()
+    fam_names = ("jacobian", "lu", "residual", "pressure")
+
+    def timed(step, nsteps, nwarm):
+        for _ in range(nwarm):
+            step()
+        torch.cuda.synchronize()
+        rbns.rb_timing_enable(s.ctx, True)
+        t0 = time.perf_counter()
+        for _ in range(nsteps):
+            step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        rbns.rb_timing_enable(s.ctx, False)
+        return t1 - t0, {f: rbns.rb_timing_read(s.ctx, f) for f in fam_names}
+
+    if name == "single_n10":
+        metric = "reduced NS solves/sec at N=10 (plain single solve, B=1 per call)"
+        out = dict(u=torch.empty(1, ts.N, **f64), iters=torch.empty(1, dtype=torch.int32, device=dev),
+                   status=torch.empty(1, dtype=torch.int32, device=dev))
+        pout = dict(p=torch.empty(1, ts.Np, **f64),
+                    pstatus=torch.empty(1, dtype=torch.int32, device=dev))
+        th1 = s.theta(mu[:1])
+
+        def step():
+            rbns.rb_theta(s.ctx, s.set, 1, mu[:1], th1["ta"], th1["tc"], th1["tf"], th1["tb"], stream)
+            s.solve(th1, out=out, tol=cfg["tol"], max_iter=cfg["max_iter"], stream=stream)
+            s.pressure(th1, out["u"], out=pout, stream=stream)
+            torch.cuda.synchronize()
+        el, fams = timed(step, max(args.steps, 200), args.warmup)
+        n = max(args.steps, 200)
+        value, steps = n / el, n
+        r = oracle.solve_batch(oracle.OracleSet(ts), mu_h[:1], pressure_np=ts.Np)
+        extra["max_rel_err_u"] = float(rel_err(out["u"].cpu().numpy(), r["u"]).max())
+        extra["max_rel_err_p"] = float(rel_err(pout["p"].cpu().numpy(), r["p"]).max())
+        extra["mean_ms_per_solve"] = 1e3 * el / n
+    elif name in ("mixed_n100", "uneven_n20_100"):
+        uneven = name == "uneven_n20_100"
+        prec = rbns.RB_PREC_F32 if uneven else rbns.RB_PREC_BF16
+        refine = 2 if uneven else args.mixed_refine if args.mixed_refine >= 0 else 3
+        dtype = "f32" if uneven else "bf16"
+        Nreq = draw_basis_sizes(cfg, B) if uneven else np.full(B, ts.N, np.int32)
+        Nd = torch.as_tensor(Nreq, device=dev, dtype=torch.int32)
+        out = dict(u=torch.empty(B, ts.N, **f64), iters=torch.empty(B, dtype=torch.int32, device=dev),
+                   status=torch.empty(B, dtype=torch.int32, device=dev))
+        pout = dict(p=torch.empty(B, ts.Np, **f64), pstatus=torch.empty(B, dtype=torch.int32, device=dev))
+
+        def step():
+            rbns.rb_theta(s.ctx, s.set, B, mu, th["ta"], th["tc"], th["tf"], th["tb"], stream)
+            if uneven:
+                s.solve_uneven(th, Nd, tol=cfg["tol"], max_iter=cfg["max_iter"], precision=prec,
+                               refine_steps=refine, out=out, stream=stream)
+            else:
+                s.solve(th, out=out, tol=cfg["tol"], max_iter=cfg["max_iter"], precision=prec,
+                        refine_steps=refine, stream=stream)
+                s.pressure(th, out["u"], out=pout, stream=stream)
+        nsteps = max(3, args.steps // 4)
+        el, fams = timed(step, nsteps, max(2, args.warmup // 2))
+        value, steps = B * nsteps / el, nsteps
+        metric = ("reduced NS solves/sec, uneven N in {20..100} in one call (FP32 + FP64 "
+                  "refinement)" if uneven else
+                  "reduced NS solves/sec at N=100 (BF16 MFMA + FP64-residual refinement, "
+                  "velocity + pressure)")
+        idx = np.linspace(0, B - 1, max(args.check, 1)).astype(int)
+        r = oracle.solve_batch(oracle.OracleSet(ts), mu_h[idx], Nreq=Nreq[idx],
+                               pressure_np=0 if uneven else ts.Np)
+        extra["max_rel_err_u"] = float(rel_err(out["u"].cpu().numpy()[idx], r["u"]).max())
+        if not uneven:
+            extra["max_rel_err_p"] = float(rel_err(pout["p"].cpu().numpy()[idx], r["p"]).max())
+        extra["checked_requests"] = int(len(idx))
+        extra["refine_steps"] = refine
+        extra["status_hist"] = np.bincount(out["status"].cpu().numpy(), minlength=5).tolist()
+        extra["iters_hist"] = np.bincount(out["iters"].cpu().numpy()).tolist()
+        K = ts.Q + ts.Qc * Nreq.astype(float)
+        its = out["iters"].cpu().numpy().astype(float)
+        jac_flops = float((2.0 * Nreq ** 2 * K * np.maximum(its - refine, 1)).sum()) * nsteps
+        res_flops = float((2.0 * Nreq ** 2 * K * refine).sum()) * nsteps
+        peak_j = 2516.6 if prec == rbns.RB_PREC_BF16 else 157.3
+        kern = {}
+        for f, (ms, n) in fams.items():
+            kern[f] = dict(total_ms=ms, launches=n)
+        if fams["jacobian"][0] > 0:
+            kern["jacobian"].update(achieved_tflops=jac_flops / (fams["jacobian"][0] * 1e-3) / 1e12,
+                                    peak_tflops=peak_j, bound="mfma")
+        if fams["residual"][0] > 0:
+            kern["residual"].update(achieved_tflops=res_flops / (fams["residual"][0] * 1e-3) / 1e12,
+                                    peak_tflops=78.6, bound="mfma")
+        dominant = max(fams, key=lambda f: fams[f][0])
+        d = kern[dominant]
+        roof = dict(bound=d.get("bound", "alu"), achieved=d.get("achieved_tflops"),
+                    peak=d.get("peak_tflops", 78.6), unit="TFLOP/s", kernel=dominant,
+                    traffic=None, kernels=kern)
+        roof["frac"] = roof["achieved"] / roof["peak"] if roof["achieved"] else None
+    elif name == "serve_n150":
+        metric = "served reduced NS solves/sec, N ~ U{20..150}, Poisson arrivals (FP32 + refinement)"
+        dtype = "f32"
+        rates = [float(x) for x in (args.serve_rates or "20000,50000,100000,200000").split(",")]
+        srv = rbns.Server(s, precision=rbns.RB_PREC_F32, refine_steps=2,
+                          max_iter=cfg["max_iter"], tol=cfg["tol"], max_batch=4096, lanes=3)
+        served = {}
+        Bp = 8192
+        mu_s = draw_mu(cfg, Bp)
+        N_s = draw_basis_sizes(cfg, Bp)
+        idx = np.arange(0, Bp, Bp // max(args.check, 1))
+        ref = oracle.solve_batch(oracle.OracleSet(ts), mu_s[idx], Nreq=N_s[idx])
+        pos = {int(b): k for k, b in enumerate(idx)}
+        try:
+            for rate in rates:
+                arr = draw_arrivals(cfg, rate, args.serve_seconds)
+                n = len(arr)
+                sel = np.arange(n) % Bp
+                lat = np.full(n, np.nan)
+                stat = np.full(n, -1, dtype=np.int64)
+                errs = []
+                got, i = 0, 0
+                t0s = time.perf_counter()
+                while i < n or got < n:
+                    now = time.perf_counter() - t0s
+                    j = int(np.searchsorted(arr, now, side="right"))
+                    if j > i:
+                        srv.submit(mu_s[sel[i:j], 0], mu_s[sel[i:j], 1], N_s[sel[i:j]],
+                                   tags=np.arange(i, j))
+                        i = j
+                    ra = srv.poll_array()
+                    if len(ra):
+                        tg = ra["tag"]
+                        lat[tg] = ra["latency_ms"]
+                        stat[tg] = ra["status"]
+                        got += len(ra)
+                        for rr in ra:
+                            m = pos.get(int(sel[int(rr["tag"])]))
+                            if m is not None and len(errs) < 4 * len(idx):
+                                nn = int(rr["N"])
+                                errs.append(float(rel_err(rr["u"][:nn], ref["u"][m, :nn])))
+                    elif i >= n:
+                        time.sleep(2e-5)
+                t1s = time.perf_counter()
+                served[f"{int(rate)}"] = dict(offered_req_s=rate, requests=n, value=n / (t1s - t0s),
+                                              p50_ms=float(np.percentile(lat, 50)),
+                                              p99_ms=float(np.percentile(lat, 99)),
+                                              max_ms=float(np.nanmax(lat)),
+                                              status_hist=np.bincount(stat, minlength=6).tolist(),
+                                              max_rel_err_u=max(errs) if errs else None)
+                log(f"[bench] served at {rate:.3g} req/s: p50 {served[f'{int(rate)}']['p50_ms']:.3f} ms, "
+                    f"p99 {served[f'{int(rate)}']['p99_ms']:.3f} ms")
+        finally:
+            srv.stop()
+        top = served[f"{int(rates[-1])}"]
+        value, steps = top["value"], len(rates)
+        extra["served"] = served
+        extra["p99_ms"] = top["p99_ms"]
+        fams = {}
+    else:
+        raise SystemExit(f"unknown workload {name}")
+
+    res = {"metric": metric, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": steps,
+           "warmup": args.warmup, "ms_per_step": None, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic",
+           "config": {"workload": name, "N": ts.N, "B": B, "Q": ts.Q, "Qc": ts.Qc,
+                      "parallelism": "single_gpu"},
+           "roofline": roof, "cpu_baseline": None, "kernel_ms": fams, **extra}
+    print(json.dumps(res), flush=True)
+    s.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -99,6 +291,10 @@ def main():
         log("bench.py: only --gpus 1 is supported (the solves are independent per parameter;"
             " DESIGN.md describes how the path would shard)")
         sys.exit(2)
+
+    if args.workload != "batched_n50":
+        other_workload(args)
+        return
 
     import torch
     from paper_1807_11866_amd import rbns

@@ -187,11 +187,13 @@ int rb_solve_uneven(rb_ctx *ctx, int set, int B, const int *N, int ldu, const do
  * rb_autotune: time the candidate tile shapes of a batch of B requests at basis size N with
  * these coefficients (device theta_a [B][Q], theta_c [B][Qc], theta_f [B][Qf]) and keep the
  * fastest for (set, N, opts->precision, batch size class ceil(log2(B/64))); later
- * rb_solve_batch / rb_solve_uneven calls of that class use it. Candidates: 2, 4, 8 or 16 row
- * splits per 64-request tile of the contraction, and (FP64, N <= 64) the pivot-row broadcast
- * of the LU (readlane or LDS). Synchronous; produces no solution.
- * rb_tuned_config: the shape in use for such a batch (defaults when never tuned: 8 splits,
- * readlane), lu_variant 0 = readlane, 1 = LDS.
+ * rb_solve_batch / rb_solve_uneven calls of that class use it. Candidates: 2, 4, 8, 16 and
+ * the default number of row splits per 64-request tile of the contraction, and (FP64,
+ * N <= 64) the pivot-row broadcast of the LU (readlane or LDS). Synchronous; produces no
+ * solution.
+ * rb_tuned_config: the shape in use for such a batch, lu_variant 0 = readlane, 1 = LDS.
+ * Defaults when never tuned: readlane, and 8 row splits (one per XCD) for batches that fill
+ * the chip, up to 64 for small ones (about 512 workgroups, at least 4 row blocks a split).
  * Errors: RB_E_INVAL, RB_E_UNSUPPORTED (FP64 beyond RB_MAX_N_F64), RB_E_DEVICE.
  */
 int rb_autotune(rb_ctx *ctx, int set, int B, int N, const double *theta_a,
@@ -221,10 +223,12 @@ int rb_recover_pressure(rb_ctx *ctx, int set, int B, int N, int Np, int ldu, int
  * once; a worker thread forms batches from whatever has arrived whenever one of its `lanes`
  * (HIP streams, each with its own device buffers) is free, so requests that arrive while
  * others are on the GPU are admitted as soon as a lane and the HBM budget allow, and the
- * batches of different lanes overlap on the device. A batch is grouped by N and each group is
- * solved as a same-N batch (theta(mu) on the device, Newton, optionally the pressure), with
- * the tile shapes a same-N rb_solve_batch call of that size would use; a request's result
- * does not depend on the other requests of its batch. rb_server_poll hands back finished
+ * batches of different lanes overlap on the device. A batch is grouped by size class (N
+ * rounded up to a multiple of 16, at most the set's N) and each group is solved as one batch
+ * of that size (theta(mu) on the device, Newton, optionally the pressure), every request as
+ * the leading N x N block of the group's system with its other unknowns held at zero; the
+ * tile shapes depend on the group only, so a request's result does not depend on the other
+ * requests of its batch. rb_server_poll hands back finished
  * results (with the latency from submission to the moment the worker saw the batch finish).
  * The tensor set stays resident; each lane keeps its buffers and workspace between batches.
  * Stop every server of a context before rb_destroy.

@@ -118,6 +118,8 @@ struct NewtonF64Args {
   const double* tf;        // [B][Qf] (used when fover == nullptr)
   const double* fover;     // [B][ldu] or nullptr
   const double* u0;        // [B][ldu] or nullptr
+  const int* nreq;         // [B] basis size of each request (<= N, the leading block of the
+                           // group's size-N system; the rest is held at zero), or nullptr
   const double* F;         // [Qf][Nm]
   const double* H;         // [Nm][Nm] or nullptr
   double* u;               // [B][ldu]
@@ -135,7 +137,8 @@ static __global__ void newton_init_kernel(NewtonF64Args a) {
     const int64_t b = idx / NP;
     const int i = idx - b * NP;
     double uv = 0.0, fv = 0.0;
-    if (b < a.B && i < N) {
+    const int nb = (a.nreq && b < a.B) ? a.nreq[b] : N;
+    if (b < a.B && i < nb) {
       if (a.u0) uv = a.u0[b * a.ldu + i];
       if (a.fover) {
         fv = a.fover[b * a.ldu + i];
@@ -183,7 +186,7 @@ static __global__ void newton_init_kernel(NewtonF64Args a) {
 // Each workgroup writes its split's partial sums; the solve kernels add the nsplit partials.
 constexpr int kTile = 64;      // requests per workgroup tile (16 per wavefront)
 constexpr int kSplit = 8;      // default row splits, one per XCD
-constexpr int kMaxSplit = 16;  // largest split count (partial-sum buffers are sized for it)
+constexpr int kMaxSplit = 64;  // largest split count (small batches split rows further)
 constexpr int kGroup = 4;      // row blocks per wavefront pass
 constexpr int kDepth = 4;      // k-steps of A operand in flight
 constexpr int kMaxKC = 40;     // longest tensor chunk held in registers (no spills at 2 waves/SIMD)
@@ -386,6 +389,7 @@ __global__ __launch_bounds__(kThreads) void lu_f64_kernel(NewtonF64Args a, int i
   const int b = blockIdx.x * kWaves + wv;
   if (b >= a.B || a.s.done[b]) return;
   const int N = a.N;
+  const int nb = a.nreq ? a.nreq[b] : N;   // this request's size; rows/columns beyond: identity
   const double* jb = a.s.J + (int64_t)b * a.s.mp;
   const double* ub = a.s.U + (int64_t)b * NP;
   double r[NP];
@@ -400,12 +404,12 @@ __global__ __launch_bounds__(kThreads) void lu_f64_kernel(NewtonF64Args a, int i
   }
 #pragma unroll
   for (int c = 0; c < NP; ++c) {
-    r[c] = (c < N && lane < N) ? r[c] : (c == lane ? 1.0 : 0.0);
+    r[c] = (c < nb && lane < nb) ? r[c] : (c == lane ? 1.0 : 0.0);
     ju = fma(r[c], ub[c], ju);
     bad |= !finite_val(r[c]);
   }
   double rhs = 0.0;
-  if (lane < N) {
+  if (lane < nb) {
     double w = 0.0;
 #pragma unroll
     for (int sp = 0; sp < a.s.nsplit; ++sp) w += a.s.Wv[((int64_t)sp * a.s.Bp + b) * NP + lane];
@@ -465,7 +469,8 @@ __global__ __launch_bounds__(kWave * W) void lu_f64_mw_kernel(NewtonF64Args a, i
     return -(0.5 * (ju + w) - a.s.Fv[(int64_t)b * NP + row]);
   };
   double nd2, nu2;
-  const int flag = mw_newton_update<double, NP, W>(jload, a.s.jslices, N, a.Nm, ub, a.H, rhs_of,
+  const int nb = a.nreq ? a.nreq[b] : N;
+  const int flag = mw_newton_update<double, NP, W>(jload, a.s.jslices, nb, a.Nm, ub, a.H, rhs_of,
                                                    sh, nd2, nu2);
   if (threadIdx.x != 0) return;
   if (flag != 0) {

@@ -255,6 +255,7 @@ struct LpNewtonArgs {
   int64_t mp;
   const float* part;       // [nsplit][Bp][NP] A(mu) u (low-precision phase)
   const double* partA;     // [nsplit][Bp][NP] A(mu) u + C(mu)(u,u) (FP64 refinement)
+  const int* nreq;         // [B] per-request basis size (<= N) or nullptr
   NewtonState s;           // FP64 iterates, f, flags
 };
 
@@ -271,6 +272,7 @@ __global__ __launch_bounds__(kThreads) void lu_lp_kernel(LpNewtonArgs a, int it)
   const int b = blockIdx.x * kWaves + wv;
   if (b >= a.B || a.s.done[b]) return;
   const int N = a.N;
+  const int nb = a.nreq ? a.nreq[b] : N;   // this request's size; rows/columns beyond: identity
   const int64_t Bp = a.s.Bp;
   const float* jb = a.J + (int64_t)b * a.mp;
   const double* ub = a.s.U + (int64_t)b * NP;
@@ -282,11 +284,11 @@ __global__ __launch_bounds__(kThreads) void lu_lp_kernel(LpNewtonArgs a, int it)
 #pragma unroll
   for (int c = 0; c < NP; ++c) {
     const float v = jb[(c < N ? c : N - 1) * N + lc];
-    r[c] = (c < N && lane < N) ? v : (c == lane ? 1.f : 0.f);
+    r[c] = (c < nb && lane < nb) ? v : (c == lane ? 1.f : 0.f);
     ju = fmaf(r[c], static_cast<float>(ub[c]), ju);
     bad |= !finite_val(r[c]);
   }
-  if (lane < N) {
+  if (lane < nb) {
     if (kRefine) {
       double g = 0.0;
 #pragma unroll
@@ -367,7 +369,8 @@ __global__ __launch_bounds__(kWave * W) void lu_lp_mw_kernel(LpNewtonArgs a, int
     return -(0.5 * (static_cast<double>(ju) + au) - f);
   };
   double nd2, nu2;
-  const int flag = mw_newton_update<float, NP, W>(jload, 1, a.N, a.Nm, ub, a.H, rhs_of, sh, nd2,
+  const int nb = a.nreq ? a.nreq[b] : N;
+  const int flag = mw_newton_update<float, NP, W>(jload, 1, nb, a.Nm, ub, a.H, rhs_of, sh, nd2,
                                                   nu2);
   if (threadIdx.x != 0) return;
   if (flag != 0) {

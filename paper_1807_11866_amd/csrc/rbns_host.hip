@@ -443,7 +443,7 @@ int enqueue_newton_lp(rb_ctx* c, Set* s, const rb::NewtonF64Args& a, bool bf16, 
   la.N = N; la.Nm = a.Nm; la.B = a.B;
   la.tol = a.tol; la.H = a.H;
   la.stag = bf16 ? 5e-2 : 1e-3;
-  la.J = J32; la.mp = mp; la.part = part32; la.partA = partA;
+  la.J = J32; la.mp = mp; la.part = part32; la.partA = partA; la.nreq = a.nreq;
   la.s = a.s;
 
   hipLaunchKernelGGL(rb::newton_init_kernel, dim3(launch_grid(Bp * NP)), dim3(256), 0, st, a);
@@ -473,13 +473,16 @@ int enqueue_newton_lp(rb_ctx* c, Set* s, const rb::NewtonF64Args& a, bool bf16, 
   return RB_OK;
 }
 
-size_t pressure_bytes(int B, int Np) {
-  return (size_t)rb::kSplit * ceil_to(B, rb::kTile) * np_bucket(Np) * sizeof(double);
+int default_nsplit(int64_t Bp, int nrows);
+
+size_t pressure_bytes(int B, int N, int Np) {
+  const int64_t Bp = ceil_to(B, rb::kTile);
+  return (size_t)default_nsplit(Bp, Np * N) * Bp * np_bucket(Np) * sizeof(double);
 }
 
 // Pressure recovery of B requests at (N, Np) (eqn sup-vvar): the pressure-operand
-// contraction (A_sv u + C_sv(u,u), kSplit partial sums at `part`, pressure_bytes long) and
-// the pivoted LU solve B(mu) p = f_s - A_sv u - C_sv(u,u).
+// contraction (A_sv u + C_sv(u,u), default_nsplit partial sums at `part`, pressure_bytes
+// long) and the pivoted LU solve B(mu) p = f_s - A_sv u - C_sv(u,u).
 int enqueue_pressure(rb_ctx* c, Set* s, int B, int N, int Np, int ldu, int ldp,
                      const double* ta, const double* tc, const double* tf, const double* tb,
                      const double* u, double* p, int* status, char* part, hipStream_t st) {
@@ -496,13 +499,13 @@ int enqueue_pressure(rb_ctx* c, Set* s, int B, int N, int Np, int ldu, int ldp,
   g.U = u; g.ldU = ldu;
   g.done = nullptr;
   g.J = nullptr; g.mp = 0; g.jstride = 0;
-  g.part = (double*)part; g.ldp = NPP; g.nsplit = rb::kSplit;
+  g.part = (double*)part; g.ldp = NPP; g.nsplit = default_nsplit(Bp, Np * N);
   rb::PressureF64Args a;
   a.Np = Np; a.Npm = s->Np; a.Qf = s->Qf; a.Qb = s->Qb; a.B = B; a.ldp = ldp; a.Bp = Bp;
   a.tf = tf; a.tb = tb;
   a.BpT = (const double*)s->BpT.p;
   a.Fs = (const double*)s->Fs.p;
-  a.part = g.part; a.nsplit = rb::kSplit;
+  a.part = g.part; a.nsplit = g.nsplit;
   a.p = p; a.status = status;
   LaunchTimer t(c, FAM_PRESSURE, st);
   if (int rc = launch_rc(rb::launch::contract_f64(rb::kModePressure, g, st), "pressure"))
@@ -519,10 +522,25 @@ int batch_class(int64_t Bp) {
   return t;
 }
 
+// Row splits per 64-request tile when no tuned shape is recorded: 8 (one per XCD, so each
+// XCD's L2 holds an eighth of the operand) for batches that fill the chip, more for small
+// batches so that about 512 workgroups still run, at least 4 row blocks per split.
+int default_nsplit(int64_t Bp, int nrows) {
+  const int64_t tiles = std::max<int64_t>(1, Bp / rb::kTile);
+  int want = rb::kSplit;
+  while (want < rb::kMaxSplit && tiles * want < 512) want *= 2;
+  const int nrb = (nrows + 15) / 16;
+  return std::max(1, std::min(want, std::max(rb::kSplit, nrb / 4)));
+}
+
+// Partial-sum slots a state region reserves so that the autotuner can try every candidate.
+int region_nsplit(int64_t Bp, int N) { return std::max(16, default_nsplit(Bp, N * N)); }
+
 Tune tune_for(rb_ctx* c, int set, int N, int precision, int64_t Bp) {
   auto it = c->tune.find(std::make_tuple(set, N, precision, batch_class(Bp)));
   if (it != c->tune.end()) return it->second;
   Tune t;
+  t.nsplit = default_nsplit(Bp, N * N);
   t.lu_lds = c->lu_lds;
   return t;
 }
@@ -541,13 +559,14 @@ int check_opts(const char* fn, const rb_solve_opts& o) {
 rb::NewtonF64Args make_args(Set* s, Pack* pk, int N, int B, int ldu, const rb_solve_opts& o,
                             const double* ta, const double* tc, const double* tf,
                             const double* fover, const double* u0, double* u, int* iters,
-                            int* status, char* region, int nsplit) {
+                            int* status, char* region, int nsplit,
+                            const int* nreq = nullptr) {
   rb::NewtonF64Args a;
   a.op = (const double*)pk->buf.p;
   a.nrb = pk->nrb; a.nks_s = pk->nks_s; a.nks = pk->nks; a.nchunk = pk->nchunk;
   a.N = N; a.Nm = s->N; a.Q = s->Q; a.Qc = s->Qc; a.Qf = s->Qf; a.B = B; a.ldu = ldu;
   a.maxit = o.max_iter; a.tol = o.tol;
-  a.ta = ta; a.tc = tc; a.tf = tf; a.fover = fover; a.u0 = u0;
+  a.ta = ta; a.tc = tc; a.tf = tf; a.fover = fover; a.u0 = u0; a.nreq = nreq;
   a.F = (const double*)s->F.p;
   a.H = s->hasH ? (const double*)s->H.p : nullptr;
   a.u = u; a.iters = iters; a.status = status;
@@ -564,7 +583,7 @@ int enqueue_solve(rb_ctx* c, Set* s, const rb::NewtonF64Args& a, const rb_solve_
   return enqueue_newton_lp(c, s, a, o.precision == RB_PREC_BF16, o.refine_steps, lp, st);
 }
 
-// Autotuner. On the batch at hand (its state region sized for kMaxSplit partial sums), time
+// Autotuner. On the batch at hand (its state region sized for region_nsplit partials), time
 // the first Newton contraction for each row-split count and, for the one-wavefront FP64 LU,
 // both pivot-row broadcasts; record the fastest shape for (set, N, precision, batch class).
 // Synchronous on st; must not run under stream capture.
@@ -583,8 +602,9 @@ int autotune_batch(rb_ctx* c, Set* s, int set, rb::NewtonF64Args a, const rb_sol
     c->event_pool.push_back(e1);
     return rc;
   };
-  a.s = carve_state(region, Bp, NP, mp, rb::kMaxSplit, jslices_for(s, N, o.precision));
-  char* lpb = region + newton_state_bytes(Bp, NP, mp, rb::kMaxSplit, a.s.jslices);
+  const int rsplit = region_nsplit(Bp, N);
+  a.s = carve_state(region, Bp, NP, mp, rsplit, jslices_for(s, N, o.precision));
+  char* lpb = region + newton_state_bytes(Bp, NP, mp, rsplit, a.s.jslices);
   auto contract = [&](int nsplit) -> int {
     a.s.nsplit = nsplit;
     if (!lp) {
@@ -622,8 +642,8 @@ int autotune_batch(rb_ctx* c, Set* s, int set, rb::NewtonF64Args a, const rb_sol
   Tune best;
   best.lu_lds = c->lu_lds;
   float best_ms = 1e30f;
-  for (int ns : {2, 4, 8, 16}) {
-    if (ns > 2 && ns > a.nrb) continue;          // more splits than row blocks
+  for (int ns : {2, 4, 8, 16, default_nsplit(Bp, N * N)}) {
+    if (ns > rsplit || (ns > 2 && ns > a.nrb)) continue;   // no slots / more splits than rows
     float ms = 0.f;
     if (int rc = timed([&] { return contract(ns); }, &ms)) return release(rc);
     if (ms < best_ms) {
@@ -845,11 +865,11 @@ int rb_autotune(rb_ctx* c, int set, int B, int N, const double* ta, const double
   if (int rc = solve_pack_f64(c, s, N, &pk)) return rc;
   const int64_t Bp = ceil_to(B, rb::kTile);
   Workspace* w;
-  if (int rc = workspace(c, stream, solve_bytes(s, N, Bp, rb::kMaxSplit, o.precision), &w))
+  if (int rc = workspace(c, stream, solve_bytes(s, N, Bp, region_nsplit(Bp, N), o.precision), &w))
     return rc;
   char* region = (char*)w->buf.p;
   rb::NewtonF64Args a = make_args(s, pk, N, B, N, o, ta, tc, tf, nullptr, nullptr, nullptr,
-                                  nullptr, nullptr, region, rb::kMaxSplit);
+                                  nullptr, nullptr, region, region_nsplit(Bp, N));
   Tune t;
   return autotune_batch(c, s, set, a, o, region, (hipStream_t)stream, &t);
 }
@@ -902,7 +922,7 @@ int rb_solve_uneven(rb_ctx* c, int set, int B, const int* Nd, int ldu, const dou
     return fail(RB_E_UNSUPPORTED, "rb_solve_uneven: FP64 solves take N <= %d (N=%d)",
                 RB_MAX_N_F64, groups.begin()->first);
 
-  // 3. layout: staging arrays, then one state region per group (sized for kMaxSplit so the
+  // 3. layout: staging arrays, then one state region per group (sized for region_nsplit so the
   //    autotuner can run in place)
   struct Group {
     int N;
@@ -934,7 +954,7 @@ int rb_solve_uneven(rb_ctx* c, int set, int B, const int* Nd, int ldu, const dou
   const size_t o_u0 = take(u0 ? Bs * Nm * 8 : 8), o_u = take(Bs * Nm * 8);
   const size_t o_it = take(Bs * 4), o_st = take(Bs * 4), o_perm = take((Bs + nbad) * 4);
   for (auto& g : gs)
-    g.region = take(solve_bytes(s, g.N, g.Bp, rb::kMaxSplit, o.precision));
+    g.region = take(solve_bytes(s, g.N, g.Bp, region_nsplit(g.Bp, g.N), o.precision));
   Workspace* w;
   if (int rc = workspace(c, stream, off, &w)) return rc;
   char* base = (char*)w->buf.p;
@@ -979,7 +999,7 @@ int rb_solve_uneven(rb_ctx* c, int set, int B, const int* Nd, int ldu, const dou
     }
     const auto key = std::make_tuple(set, g.N, o.precision, batch_class(g.Bp));
     if (c->autotune && !c->tune.count(key)) {
-      if (int rc = autotune_batch(c, s, set, args_of(g, rb::kMaxSplit), o, base + g.region, st,
+      if (int rc = autotune_batch(c, s, set, args_of(g, region_nsplit(g.Bp, g.N)), o, base + g.region, st,
                                   &g.t))
         return rc;
     }
@@ -1095,7 +1115,7 @@ int rb_recover_pressure(rb_ctx* c, int set, int B, int N, int Np, int ldu, int l
   std::lock_guard<std::mutex> lk(c->mu);
   if (int rc = use_device(c)) return rc;
   Workspace* w;
-  if (int rc = workspace(c, stream, pressure_bytes(B, Np), &w)) return rc;
+  if (int rc = workspace(c, stream, pressure_bytes(B, N, Np), &w)) return rc;
   return enqueue_pressure(c, s, B, N, Np, ldu, ldp, ta, tc, tf, tb, u, p, status,
                           (char*)w->buf.p, (hipStream_t)stream);
 }
@@ -1152,15 +1172,23 @@ struct Pending {
   Clock::time_point t_submit;
 };
 
-// One lane: a stream, its device buffers for max_batch requests and pinned host mirrors.
+// One lane: a stream, its device buffers for max_batch requests and pinned host mirrors. The
+// size-class groups of a batch run concurrently on the lane's sub-streams (forked from and
+// joined back into the lane stream with events).
+constexpr int kSubStreams = 4;
+
 struct Lane {
   hipStream_t st = nullptr;
   hipEvent_t done = nullptr;
+  hipStream_t sub[kSubStreams] = {};
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[kSubStreams] = {};
   bool busy = false;
   size_t need = 0;                    // workspace estimate of the batch in flight
   std::vector<Pending> batch;         // in the order of the device rows (grouped by N)
-  DevBuf d_mu, d_ta, d_tc, d_tf, d_tb, d_u, d_p, d_int;
+  DevBuf d_mu, d_ta, d_tc, d_tf, d_tb, d_u, d_p, d_int, d_n;
   double* h_mu = nullptr;             // pinned [cap][2]
+  int* h_n = nullptr;                 // pinned [cap]: basis size of each row
   double* h_u = nullptr;              // pinned [cap][Nm]
   double* h_p = nullptr;              // pinned [cap][Np]
   int* h_int = nullptr;               // pinned [3][cap]: iters, status, pstatus
@@ -1191,6 +1219,13 @@ struct rb_server {
 
 namespace {
 
+// Group size of a served request of basis size n: n rounded up to a multiple of 16 (at most
+// the set's N). A request is solved as the leading n x n block of its group's system (the
+// remaining unknowns held at zero by identity rows), so a batch with many distinct sizes runs
+// a handful of group chains; the group depends on n only, so a request's result does not
+// depend on the rest of its batch.
+int serve_group(int n, int Nm) { return (int)std::min<int64_t>(Nm, ceil_to(n, 16)); }
+
 // Workspace of one batch: per N group the Newton state (tile shapes of a same-N batch of that
 // size) and, with pressure, the pressure partial sums.
 size_t batch_bytes(rb_server* v, const std::vector<std::pair<int, int>>& groups) {
@@ -1200,7 +1235,7 @@ size_t batch_bytes(rb_server* v, const std::vector<std::pair<int, int>>& groups)
     const int64_t Bp = ceil_to(g.second, rb::kTile);
     const Tune t = tune_for(v->c, v->set, N, v->o.precision, Bp);
     b += solve_bytes(v->s, N, Bp, t.nsplit, v->o.precision);
-    if (v->o.pressure) b += (size_t)ceil_to((int64_t)pressure_bytes(g.second, v->s->Np), 256);
+    if (v->o.pressure) b += (size_t)ceil_to((int64_t)pressure_bytes(g.second, N, v->s->Np), 256);
   }
   return b;
 }
@@ -1214,9 +1249,11 @@ int launch_batch(rb_server* v, Lane& L) {
   for (int i = 0; i < B; ++i) {
     L.h_mu[2 * i] = L.batch[i].alpha;
     L.h_mu[2 * i + 1] = L.batch[i].re;
+    L.h_n[i] = L.batch[i].N;
   }
   HIP_TRY(hipMemcpyAsync(L.d_mu.p, L.h_mu, (size_t)B * 2 * sizeof(double), hipMemcpyHostToDevice,
                          L.st));
+  HIP_TRY(hipMemcpyAsync(L.d_n.p, L.h_n, (size_t)B * sizeof(int), hipMemcpyHostToDevice, L.st));
   const int Qb = Np > 0 ? s->Qb : 1;
   double* ta = (double*)L.d_ta.p;
   double* tc = (double*)L.d_tc.p;
@@ -1225,16 +1262,20 @@ int launch_batch(rb_server* v, Lane& L) {
   hipLaunchKernelGGL(rb::theta_kernel, dim3((B + 255) / 256), dim3(256), 0, L.st,
                      (const double*)L.d_mu.p, B, s->Q, s->Qc, s->Qf, Qb, ta, tc, tf,
                      Np > 0 ? tb : nullptr);
-  std::vector<std::pair<int, int>> groups;   // (N, count), rows contiguous
+  std::vector<std::pair<int, int>> groups;   // (group size, count), rows contiguous
   for (int i = 0; i < B;) {
+    const int gN = serve_group(L.batch[i].N, Nm);
     int j = i;
-    while (j < B && L.batch[j].N == L.batch[i].N) ++j;
-    groups.push_back({L.batch[i].N, j - i});
+    while (j < B && serve_group(L.batch[j].N, Nm) == gN) ++j;
+    groups.push_back({gN, j - i});
     i = j;
   }
   Workspace* w;
   if (int rc = workspace(c, L.st, batch_bytes(v, groups), &w)) return rc;
   char* base = (char*)w->buf.p;
+  HIP_TRY(hipEventRecord(L.fork, L.st));
+  const int nsub = std::min<int>(kSubStreams, (int)groups.size());
+  for (int k = 0; k < nsub; ++k) HIP_TRY(hipStreamWaitEvent(L.sub[k], L.fork, 0));
   double* u = (double*)L.d_u.p;
   double* p = (double*)L.d_p.p;
   int* it = (int*)L.d_int.p;
@@ -1242,7 +1283,9 @@ int launch_batch(rb_server* v, Lane& L) {
   int* pst = it + 2 * v->cap;
   rb_solve_opts o = {v->o.tol, v->o.max_iter, v->o.precision, v->o.refine_steps};
   int r0 = 0;
-  for (auto& g : groups) {
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    const auto& g = groups[gi];
+    hipStream_t gst = L.sub[gi % kSubStreams];
     const int N = g.first, n = g.second;
     const int64_t Bp = ceil_to(n, rb::kTile);
     Pack* pk;
@@ -1251,18 +1294,22 @@ int launch_batch(rb_server* v, Lane& L) {
     rb::NewtonF64Args a =
         make_args(s, pk, N, n, Nm, o, ta + (int64_t)r0 * s->Q, tc + (int64_t)r0 * s->Qc,
                   tf + (int64_t)r0 * s->Qf, nullptr, nullptr, u + (int64_t)r0 * Nm, it + r0,
-                  stt + r0, base, t.nsplit);
-    if (int rc = enqueue_solve(c, s, a, o, t, base, L.st)) return rc;
+                  stt + r0, base, t.nsplit, (const int*)L.d_n.p + r0);
+    if (int rc = enqueue_solve(c, s, a, o, t, base, gst)) return rc;
     base += solve_bytes(s, N, Bp, t.nsplit, o.precision);
     if (v->o.pressure) {
       if (int rc = enqueue_pressure(c, s, n, N, Np, Nm, Np, ta + (int64_t)r0 * s->Q,
                                     tc + (int64_t)r0 * s->Qc, tf + (int64_t)r0 * s->Qf,
                                     tb + (int64_t)r0 * s->Qb, u + (int64_t)r0 * Nm,
-                                    p + (int64_t)r0 * Np, pst + r0, base, L.st))
+                                    p + (int64_t)r0 * Np, pst + r0, base, gst))
         return rc;
-      base += (size_t)ceil_to((int64_t)pressure_bytes(n, Np), 256);
+      base += (size_t)ceil_to((int64_t)pressure_bytes(n, N, Np), 256);
     }
     r0 += n;
+  }
+  for (int k = 0; k < nsub; ++k) {
+    HIP_TRY(hipEventRecord(L.join[k], L.sub[k]));
+    HIP_TRY(hipStreamWaitEvent(L.st, L.join[k], 0));
   }
   HIP_TRY(hipMemcpyAsync(L.h_u, u, (size_t)B * Nm * sizeof(double), hipMemcpyDeviceToHost, L.st));
   HIP_TRY(hipMemcpyAsync(L.h_int, it, (size_t)3 * v->cap * sizeof(int), hipMemcpyDeviceToHost, L.st));
@@ -1344,12 +1391,15 @@ void serve(rb_server* v) {
         take.push_back(q);
       }
       if (take.empty()) continue;
-      std::stable_sort(take.begin(), take.end(),
-                       [](const Pending& x, const Pending& y) { return x.N > y.N; });
-      auto groups_of = [](const std::vector<Pending>& t, size_t n) {
+      const int Nm = v->s->N;
+      std::stable_sort(take.begin(), take.end(), [Nm](const Pending& x, const Pending& y) {
+        return serve_group(x.N, Nm) > serve_group(y.N, Nm);
+      });
+      auto groups_of = [Nm](const std::vector<Pending>& t, size_t n) {
         std::vector<std::pair<int, int>> g;
         for (size_t i = 0; i < n; ++i) {
-          if (g.empty() || g.back().first != t[i].N) g.push_back({t[i].N, 0});
+          const int gN = serve_group(t[i].N, Nm);
+          if (g.empty() || g.back().first != gN) g.push_back({gN, 0});
           ++g.back().second;
         }
         return g;
@@ -1376,6 +1426,7 @@ void serve(rb_server* v) {
       const int rc = launch_batch(v, L);
       if (rc != RB_OK) {
         v->error = g_err;
+        for (int k = 0; k < kSubStreams; ++k) (void)hipStreamSynchronize(L.sub[k]);
         (void)hipStreamSynchronize(L.st);
         harvest(v, L, true);
       }
@@ -1396,11 +1447,16 @@ void serve(rb_server* v) {
 
 void free_lanes(rb_server* v) {
   for (auto& L : v->lanes) {
-    for (DevBuf* b : {&L.d_mu, &L.d_ta, &L.d_tc, &L.d_tf, &L.d_tb, &L.d_u, &L.d_p, &L.d_int})
+    for (DevBuf* b : {&L.d_mu, &L.d_ta, &L.d_tc, &L.d_tf, &L.d_tb, &L.d_u, &L.d_p, &L.d_int, &L.d_n})
       dev_free(v->c, *b);
-    for (void* h : {(void*)L.h_mu, (void*)L.h_u, (void*)L.h_p, (void*)L.h_int})
+    for (void* h : {(void*)L.h_mu, (void*)L.h_u, (void*)L.h_p, (void*)L.h_int, (void*)L.h_n})
       if (h) (void)hipHostFree(h);
     if (L.done) (void)hipEventDestroy(L.done);
+    if (L.fork) (void)hipEventDestroy(L.fork);
+    for (int k = 0; k < kSubStreams; ++k) {
+      if (L.join[k]) (void)hipEventDestroy(L.join[k]);
+      if (L.sub[k]) (void)hipStreamDestroy(L.sub[k]);
+    }
     if (L.st) {
       auto it = v->c->ws.find((void*)L.st);
       if (it != v->c->ws.end()) {
@@ -1447,8 +1503,13 @@ int rb_server_start(rb_ctx* c, int set, const rb_server_opts* opts, rb_server** 
     for (auto& L : v->lanes) {
       int rc = RB_OK;
       if (hipStreamCreateWithFlags(&L.st, hipStreamNonBlocking) != hipSuccess ||
-          hipEventCreateWithFlags(&L.done, hipEventDisableTiming) != hipSuccess)
+          hipEventCreateWithFlags(&L.done, hipEventDisableTiming) != hipSuccess ||
+          hipEventCreateWithFlags(&L.fork, hipEventDisableTiming) != hipSuccess)
         rc = fail(RB_E_DEVICE, "rb_server_start: stream/event creation failed");
+      for (int k = 0; k < kSubStreams && !rc; ++k)
+        if (hipStreamCreateWithFlags(&L.sub[k], hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&L.join[k], hipEventDisableTiming) != hipSuccess)
+          rc = fail(RB_E_DEVICE, "rb_server_start: stream/event creation failed");
       if (!rc) rc = dev_alloc(c, L.d_mu, cap * 2 * 8);
       if (!rc) rc = dev_alloc(c, L.d_ta, cap * s->Q * 8);
       if (!rc) rc = dev_alloc(c, L.d_tc, cap * s->Qc * 8);
@@ -1457,10 +1518,12 @@ int rb_server_start(rb_ctx* c, int set, const rb_server_opts* opts, rb_server** 
       if (!rc) rc = dev_alloc(c, L.d_u, cap * Nm * 8);
       if (!rc) rc = dev_alloc(c, L.d_p, cap * Np * 8);
       if (!rc) rc = dev_alloc(c, L.d_int, cap * 3 * 4);
+      if (!rc) rc = dev_alloc(c, L.d_n, cap * 4);
       if (!rc && (hipHostMalloc((void**)&L.h_mu, cap * 2 * 8, hipHostMallocDefault) != hipSuccess ||
                   hipHostMalloc((void**)&L.h_u, cap * Nm * 8, hipHostMallocDefault) != hipSuccess ||
                   hipHostMalloc((void**)&L.h_p, cap * Np * 8, hipHostMallocDefault) != hipSuccess ||
-                  hipHostMalloc((void**)&L.h_int, cap * 3 * 4, hipHostMallocDefault) != hipSuccess))
+                  hipHostMalloc((void**)&L.h_int, cap * 3 * 4, hipHostMallocDefault) != hipSuccess ||
+                  hipHostMalloc((void**)&L.h_n, cap * 4, hipHostMallocDefault) != hipSuccess))
         rc = fail(RB_E_NOMEM, "rb_server_start: pinned host buffers");
       if (rc) {
         free_lanes(v.get());
@@ -1563,8 +1626,11 @@ int rb_server_stop(rb_server* v) {
   {
     std::lock_guard<std::mutex> ck(v->c->mu);
     (void)hipSetDevice(v->c->device);
-    for (auto& L : v->lanes)
+    for (auto& L : v->lanes) {
+      for (int k = 0; k < kSubStreams; ++k)
+        if (L.sub[k]) (void)hipStreamSynchronize(L.sub[k]);
       if (L.st) (void)hipStreamSynchronize(L.st);
+    }
     free_lanes(v);
   }
   delete v;

@@ -132,7 +132,7 @@ def test_autotune_choice_is_used_and_exact(oracle_lib, R, c2):
     s = R.Solver(c2)
     th = s.theta(_dev(mu))
     ns, lv = s.autotune(th)
-    assert ns in (2, 4, 8, 16) and lv in (0, 1)
+    assert 1 <= ns <= 64 and lv in (0, 1)
     assert R.rb_tuned_config(s.ctx, s.set, 50, R.RB_PREC_F64, 512) == (ns, lv)
     out = s.solve(th)
     torch.cuda.synchronize()
