@@ -203,8 +203,9 @@ namespace rb {
 // parity), candidate values and positions, and the solution vector.
 template <int NP, int W, typename T>
 struct GjShared {
-  static constexpr int kRow = (NP + 1 + 3) & ~3;   // pivot row + right-hand side, padded
-  T rows[2][W][kRow];
+  static constexpr int kVec = 16 / sizeof(T);      // elements per 16-byte LDS access
+  static constexpr int kRow = (NP + 1 + kVec - 1) / kVec * kVec;   // pivot row + rhs, padded
+  __attribute__((aligned(16))) T rows[2][W][kRow];
   T cv[2][W];
   int cp[2][W];
   T xs[NP];
@@ -227,6 +228,8 @@ template <int NP, int W, typename T>
 __device__ __forceinline__ int gj_solve_mw(T (&a)[NP], T rhs, int row, int lane, int wv,
                                            GjShared<NP, W, T>& sh) {
   constexpr int kRow = GjShared<NP, W, T>::kRow;
+  constexpr int kVec = GjShared<NP, W, T>::kVec;
+  typedef T vec_t __attribute__((ext_vector_type(kVec)));
   int pos = row;
   bool singular = false;
   T mypiv = T(1);
@@ -246,10 +249,15 @@ __device__ __forceinline__ int gj_solve_mw(T (&a)[NP], T rhs, int row, int lane,
         if (p2 < best) { best = p2; pl = l2; }
       }
     }
-    if (lane == pl) {
+    if (lane == pl) {                     // 16-byte stores of a[k..NP) and the rhs
 #pragma unroll
-      for (int j = k & ~3; j < NP; ++j) sh.rows[buf][wv][j] = a[j];
-      sh.rows[buf][wv][NP] = rhs;
+      for (int j0 = k & ~(kVec - 1); j0 < kRow; j0 += kVec) {
+        vec_t v;
+#pragma unroll
+        for (int t = 0; t < kVec; ++t)
+          v[t] = j0 + t < NP ? a[j0 + t < NP ? j0 + t : 0] : (j0 + t == NP ? rhs : T(0));
+        *reinterpret_cast<vec_t*>(&sh.rows[buf][wv][j0]) = v;
+      }
     }
     const int ppos_w = pl >= 0 ? bcast(pos, pl) : 0x7fffffff;
     if (lane == 0) {
@@ -279,15 +287,19 @@ __device__ __forceinline__ int gj_solve_mw(T (&a)[NP], T rhs, int row, int lane,
     mypiv = me ? piv : mypiv;
     const T l = me ? T(0) : a[k] / piv;
 #pragma unroll
-    for (int j0 = k + 1; j0 < kRow; j0 += 8) {
-      T pj[8];
+    for (int j0 = (k + 1) & ~(kVec - 1); j0 < kRow; j0 += 2 * kVec) {
+      vec_t pj[2];
 #pragma unroll
-      for (int t = 0; t < 8; ++t)
-        if (j0 + t <= NP) pj[t] = pr[j0 + t];
+      for (int h2 = 0; h2 < 2; ++h2)
+        if (j0 + h2 * kVec < kRow) pj[h2] = *reinterpret_cast<const vec_t*>(&pr[j0 + h2 * kVec]);
 #pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        if (j0 + t < NP) a[j0 + t] = fma(-l, pj[t], a[j0 + t]);
-        else if (j0 + t == NP) rhs = fma(-l, pj[t], rhs);
+      for (int h2 = 0; h2 < 2; ++h2) {
+#pragma unroll
+        for (int t = 0; t < kVec; ++t) {
+          const int j = j0 + h2 * kVec + t;
+          if (j > k && j < NP) a[j] = fma(-l, pj[h2][t], a[j]);
+          else if (j == NP) rhs = fma(-l, pj[h2][t], rhs);
+        }
       }
       __builtin_amdgcn_sched_barrier(0);
     }

@@ -3,8 +3,9 @@
 Each uneven result is compared with the FP64 oracle at the request's own N (1e-10 on the FP64
 path, 1e-8 after mixed-precision refinement) and with the same request solved in a same-N
 batch (1e-12: the two differ only in the order of floating-point sums when the tile shapes
-differ). The same shape is solved three times, so the plain, capturing and replaying paths are
-all covered.
+differ). The same shape is solved five times with other parameters and eager work between
+the calls, so the plain, capturing and replaying paths are all covered and every replay is
+checked.
 """
 
 import numpy as np
@@ -61,7 +62,7 @@ def test_uneven_fp32_three_calls_same_shape(oracle_lib, R, c3):
     cfg = get_config("uneven_n20_100")
     Nreq = draw_basis_sizes(cfg, 700)
     s = R.Solver(c3)
-    for call in range(3):
+    for call in range(5):                 # plain, capture + replay, then replays
         mu = draw_mu(cfg, 700, seed_offset=call)
         th = s.theta(_dev(mu))
         g = _uneven(R, s, th, Nreq, precision=R.RB_PREC_F32, refine_steps=2)
@@ -73,6 +74,9 @@ def test_uneven_fp32_three_calls_same_shape(oracle_lib, R, c3):
         assert np.max(err) <= 1e-8, (call, np.max(err))
         for b in range(0, 700, 97):                 # zero beyond each request's own N
             assert not np.any(g["u"][b, Nreq[b]:])
+        # eager work on the same stream between the graph replays
+        s.solve(s.theta(_dev(mu[:50])), N=20, precision=R.RB_PREC_F32, refine_steps=1)
+        torch.cuda.synchronize()
     # the same requests in same-N batches
     for n in np.unique(Nreq):
         idx = np.nonzero(Nreq == n)[0]
