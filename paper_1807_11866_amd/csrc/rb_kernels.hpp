@@ -166,8 +166,8 @@ static __global__ void newton_init_kernel(NewtonF64Args a) {
 // W (the B operand: the affine k-steps and one chunk of at most kMaxKC tensor k-steps) in
 // registers, so the main loop touches no LDS; the four wavefronts walk the same row blocks in
 // the same order and share each A tile (one 512-byte line per k-step and row block) through
-// L1. Row blocks go four at a time; every k-step issues the four A loads kDepth k-steps ahead
-// and four v_mfma_f64_16x16x4f64. The k loop is unrolled at its compile-time length, and the
+// L1. Row blocks go kGroup at a time; every k-step issues their A loads kDepth k-steps ahead
+// and kGroup v_mfma_f64_16x16x4f64. The k loop is unrolled at its compile-time length, and the
 // loads of the next group of row blocks are issued during the tail of the current one, so the
 // pipeline does not drain between groups. The affine part is padded to kAmax = 3 k-steps
 // (zero columns) so that every row block has the same static pipeline. Tensor parts longer
@@ -187,8 +187,8 @@ static __global__ void newton_init_kernel(NewtonF64Args a) {
 constexpr int kTile = 64;      // requests per workgroup tile (16 per wavefront)
 constexpr int kSplit = 8;      // default row splits, one per XCD
 constexpr int kMaxSplit = 64;  // largest split count (small batches split rows further)
-constexpr int kGroup = 4;      // row blocks per wavefront pass
-constexpr int kDepth = 4;      // k-steps of A operand in flight
+constexpr int kGroup = 2;      // row blocks per wavefront pass
+constexpr int kDepth = 6;      // k-steps of A operand in flight
 constexpr int kMaxKC = 40;     // longest tensor chunk held in registers (no spills at 2 waves/SIMD)
 constexpr int kAmax = 3;       // affine k-steps of every packed row block (Q <= 12)
 

@@ -1004,6 +1004,9 @@ int rb_solve_uneven(rb_ctx* c, int set, int B, const int* Nd, int ldu, const dou
         return rc;
     }
     g.t = tune_for(c, set, g.N, o.precision, g.Bp);
+    // a shape tuned on another batch of the same size class may ask for more partial-sum
+    // slots than this group's region holds
+    g.t.nsplit = std::min(g.t.nsplit, region_nsplit(g.Bp, g.N));
   }
 
   // 6. the group chains: replayed from a captured graph when this shape has been seen before
