@@ -108,46 +108,75 @@ __device__ __forceinline__ void wave_lds_order() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Search key of a pivot candidate: the high 32 bits of |a| (monotonic in |a| for doubles,
+// the whole value for floats), so the wavefront maximum is a 32-bit DPP reduction.
+__device__ __forceinline__ uint32_t pivot_key(double av) {
+  return static_cast<uint32_t>(static_cast<uint64_t>(__double_as_longlong(av)) >> 32);
+}
+__device__ __forceinline__ uint32_t pivot_key(float av) { return __float_as_uint(av); }
+
+// Wavefront maximum of an unsigned key (row_shr 1,2,4,8, row_bcast 15/31), in every lane.
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+  v = max(v, static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x111, 0xf, 0xf, true)));
+  v = max(v, static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x112, 0xf, 0xf, true)));
+  v = max(v, static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x114, 0xf, 0xf, true)));
+  v = max(v, static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x118, 0xf, 0xf, true)));
+  v = max(v, static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x142, 0xa, 0xf, true)));
+  v = max(v, static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(v), 0x143, 0xc, 0xf, true)));
+  return static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(v), 63));
+}
+
 // Dense solve of one N x N system held one row per lane (row i in lane i, NP >= N columns
-// in registers), by Gaussian elimination with partial pivoting. The caller pads the system
-// to NP x NP with identity rows/columns (lanes N..NP-1) and a zero right-hand side there;
-// the padded rows never win a pivot search in the first N columns and pivot on themselves
-// afterwards, so every step runs unconditionally (no data-dependent control flow around the
-// register-resident rows). Rows are not moved between lanes: `pos` tracks each row's current
-// position so that the pivot choice (largest magnitude, ties to the smallest current row
-// index) is the one row-swapping elimination makes. The pivot row reaches the other lanes
-// either through `prow` (this wavefront's LDS row, >= NP + 1 entries; kLdsBcast) or lane by
-// lane through scalar registers (readlane); the right-hand side rides along as an extra
-// column. On return lane c < NP holds x_c in `x`. Returns 0, or RB_ST_SINGULAR (2)
-// if a pivot was zero (the values returned are then meaningless).
+// in registers), by Gauss-Jordan elimination with partial pivoting: at step k column k is
+// eliminated from every row but the pivot row, so no back substitution is needed. The caller
+// pads the system to NP x NP with identity rows/columns (lanes N..NP-1) and a zero
+// right-hand side there; the padded rows never win a pivot search in the first N columns and
+// pivot on themselves afterwards, so every step runs unconditionally. Rows are not moved
+// between lanes: `pos` tracks each row's position under row swaps, and the pivot is the one
+// partial pivoting picks: the largest magnitude among the rows at positions >= k, ties to
+// the smallest position (the wavefront maximum of pivot_key, then an exact comparison among
+// the lanes sharing the maximal key). The pivot row reaches the other lanes either through
+// `prow` (this wavefront's LDS row, >= NP + 1 entries; kLdsBcast) or lane by lane through
+// scalar registers (readlane); the right-hand side rides along as an extra column. Finally
+// the row at position k holds x_k * pivot_k; `prow` serves to put x back in lane order. On
+// return lane c < NP holds x_c in `x`. Returns 0, or RB_ST_SINGULAR (2) if a pivot was zero
+// (the values returned are then meaningless).
 template <int NP, bool kLdsBcast, typename T>
 __device__ __forceinline__ int lu_solve_rows(T (&a)[NP], T rhs, int lane, T* prow, T& x) {
   int pos = lane;
   bool singular = false;
+  T mypiv = T(1);
 #pragma unroll
   for (int k = 0; k < NP; ++k) {
-    T v = (pos >= k && lane < NP) ? absv(a[k]) : T(-1);
-    if (!(v == v)) v = static_cast<T>(__builtin_huge_val());  // a NaN pivot surfaces
-    const T vmax = wave_max_pos(v);
-    const uint64_t tied = __ballot(v == vmax);
+    const bool cand = pos >= k && lane < NP;
+    const T av = absv(a[k]);
+    uint32_t key = cand ? pivot_key(av) : 0u;
+    if (cand && !(av == av)) key = 0xffffffffu;    // a NaN pivot surfaces
+    if (cand && key == 0u) key = 1u;               // zero candidates still beat non-candidates
+    const uint32_t kmax = wave_max_u32(key);
+    const uint64_t tied = __ballot(key == kmax);
     int pv = __ffsll(static_cast<unsigned long long>(tied)) - 1;
-    if (__popcll(tied) > 1) {            // exact tie (rare): smallest current position wins
+    if (__popcll(tied) > 1) {        // same key: exact magnitude, then smallest position
+      T bv = bcast(av, pv);
       int best = bcast(pos, pv);
       for (uint64_t m = tied & (tied - 1); m; m &= m - 1) {
         const int l2 = __ffsll(static_cast<unsigned long long>(m)) - 1;
+        const T v2 = bcast(av, l2);
         const int p2 = bcast(pos, l2);
-        if (p2 < best) { best = p2; pv = l2; }
+        if (v2 > bv || (v2 == bv && p2 < best)) { bv = v2; best = p2; pv = l2; }
       }
     }
     T piv = bcast(a[k], pv);
     singular |= (piv == T(0));
     piv = (piv == T(0)) ? T(1) : piv;
     const int ppos = bcast(pos, pv);
+    const bool me = lane == pv;
     pos = (pos == k) ? ppos : pos;
-    pos = (lane == pv) ? k : pos;
-    const T l = (pos > k) ? a[k] / piv : T(0);
+    pos = me ? k : pos;
+    mypiv = me ? piv : mypiv;
+    const T l = me ? T(0) : a[k] / piv;
     if (kLdsBcast) {
-      if (lane == pv) {
+      if (me) {
 #pragma unroll
         for (int j = k + 1; j < NP; ++j) prow[j] = a[j];
         prow[NP] = rhs;
@@ -179,19 +208,10 @@ __device__ __forceinline__ int lu_solve_rows(T (&a)[NP], T rhs, int lane, T* pro
       rhs = fma(-l, bcast(rhs, pv), rhs);
     }
   }
-  // Back substitution: the row that pivoted at step k (pos == k) holds U[k][k..] and the
-  // eliminated right-hand side; x_k = rhs / U[k][k], then every earlier pivot row drops its
-  // x_k term.
-  x = T(0);
-#pragma unroll
-  for (int k = NP - 1; k >= 0; --k) {
-    const int p = __ffsll(static_cast<unsigned long long>(__ballot(pos == k))) - 1;
-    T d = bcast(a[k], p);
-    d = (d == T(0)) ? T(1) : d;
-    const T xk = bcast(rhs, p) / d;
-    rhs = (pos < k) ? fma(-a[k], xk, rhs) : rhs;
-    x = (lane == k) ? xk : x;
-  }
+  if (lane < NP) prow[pos] = rhs / mypiv;
+  wave_lds_order();
+  x = lane < NP ? prow[lane] : T(0);
+  wave_lds_order();
   return singular ? 2 : 0;
 }
 
