@@ -256,19 +256,25 @@ __device__ __forceinline__ int gj_solve_mw(T (&a)[NP], T rhs, int row, int lane,
 #pragma unroll
   for (int k = 0; k < NP; ++k) {
     const int buf = k & 1;
-    T v = (pos >= k && row < NP) ? absv(a[k]) : T(-1);
-    if (!(v == v)) v = static_cast<T>(__builtin_huge_val());
-    const T vmax = wave_max_pos(v);
-    const uint64_t tied = __ballot(v == vmax);
+    const bool cand = pos >= k && row < NP;
+    const T av = absv(a[k]);
+    uint32_t key = cand ? pivot_key(av) : 0u;
+    if (cand && !(av == av)) key = 0xffffffffu;    // a NaN pivot surfaces
+    if (cand && key == 0u) key = 1u;               // zero candidates still beat non-candidates
+    const uint32_t kmax = wave_max_u32(key);
+    const uint64_t tied = kmax ? __ballot(key == kmax) : 0ull;   // none: no candidate here
     int pl = tied ? __ffsll(static_cast<unsigned long long>(tied)) - 1 : -1;
-    if (pl >= 0 && __popcll(tied) > 1) {
+    T vmax = pl >= 0 ? bcast(av, pl) : T(-1);
+    if (pl >= 0 && __popcll(tied) > 1) {  // same key: exact magnitude, then smallest position
       int best = bcast(pos, pl);
       for (uint64_t m = tied & (tied - 1); m; m &= m - 1) {
         const int l2 = __ffsll(static_cast<unsigned long long>(m)) - 1;
+        const T v2 = bcast(av, l2);
         const int p2 = bcast(pos, l2);
-        if (p2 < best) { best = p2; pl = l2; }
+        if (v2 > vmax || (v2 == vmax && p2 < best)) { vmax = v2; best = p2; pl = l2; }
       }
     }
+    if (pl >= 0 && !(vmax == vmax)) vmax = static_cast<T>(__builtin_huge_val());
     if (lane == pl) {                     // 16-byte stores of a[k..NP) and the rhs
 #pragma unroll
       for (int j0 = k & ~(kVec - 1); j0 < kRow; j0 += kVec) {
