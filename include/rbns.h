@@ -58,8 +58,8 @@ typedef struct rb_ctx rb_ctx;
 
 /*
  * Reduced operators of one parameterised model (host pointers, FP64, copied on load).
- * Sizes are the stored maxima; bases are nested, so a solve at basis size N <= N uses the
- * leading N x N (x N) blocks. Index meaning (row index = test function, as in a Galerkin
+ * Sizes are the stored maxima; bases are nested, so a solve at basis size n <= N uses the
+ * leading n x n (x n) blocks. Index meaning (row index = test function, as in a Galerkin
  * matrix; paper eqn tensor writes C^i_{jkl} = c_i(u_j, u_k, u_l), i.e. C_q[l][j][k] here):
  *   A   [Q][N][N]        A_q[i][j]      = a_q(phi_j, phi_i)
  *   C   [Qc][N][N][N]    C_q[i][j][k]   = c_q(phi_j, phi_k, phi_i)   (j advects, k advected)
@@ -182,6 +182,20 @@ int rb_solve_uneven(rb_ctx *ctx, int set, int B, const int *N, int ldu, const do
                     const double *theta_c, const double *theta_f, const double *f_override,
                     const double *u0, const rb_solve_opts *opts, double *u, int *iters,
                     int *status, void *hip_stream);
+
+/*
+ * rb_recover_pressure_uneven: like rb_recover_pressure, but each request b has its own
+ * velocity basis size N[b] (device int [B]; pressure size Np for all); rows of u have stride
+ * ldu >= the set's N, rows of p stride ldp >= Np. The call copies N to the host (it waits for
+ * the work already queued on hip_stream), groups the requests by N, recovers each group's
+ * pressure and scatters p and status back in the caller's order. Requests with N[b] outside
+ * [1, set N] get status RB_ST_BADN and p = 0.
+ * Errors: as rb_recover_pressure.
+ */
+int rb_recover_pressure_uneven(rb_ctx *ctx, int set, int B, const int *N, int Np, int ldu,
+                               int ldp, const double *theta_a, const double *theta_c,
+                               const double *theta_f, const double *theta_b, const double *u,
+                               double *p, int *status, void *hip_stream);
 
 /*
  * rb_autotune: time the candidate tile shapes of a batch of B requests at basis size N with

@@ -522,10 +522,14 @@ struct UnevenIo {
   double* u;               // caller results [B][ldu], [B], [B]
   int* iters;
   int* status;
+  const double* tb;        // pressure coefficients theta^b [B][Qb] or nullptr
+  double* tb_s;            // staging [Bs][Qb]
+  int Qb;
 };
 
 static __global__ void uneven_gather_kernel(UnevenIo g) {
-  const int w = g.Q + g.Qc + (g.fover ? 0 : g.Qf);
+  const int wf = g.Q + g.Qc + (g.fover ? 0 : g.Qf);
+  const int w = wf + (g.tb ? g.Qb : 0);
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < g.Bs * w; idx += stride) {
     const int64_t r = idx / w;
@@ -533,7 +537,8 @@ static __global__ void uneven_gather_kernel(UnevenIo g) {
     const int b = g.perm[r];
     if (k < g.Q) g.ta_s[r * g.Q + k] = b >= 0 ? g.ta[(int64_t)b * g.Q + k] : 0.0;
     else if (k < g.Q + g.Qc) g.tc_s[r * g.Qc + k - g.Q] = b >= 0 ? g.tc[(int64_t)b * g.Qc + k - g.Q] : 0.0;
-    else g.f_s[r * g.Qf + k - g.Q - g.Qc] = b >= 0 ? g.tf[(int64_t)b * g.Qf + k - g.Q - g.Qc] : 0.0;
+    else if (k < wf) g.f_s[r * g.Qf + k - g.Q - g.Qc] = b >= 0 ? g.tf[(int64_t)b * g.Qf + k - g.Q - g.Qc] : 0.0;
+    else g.tb_s[r * g.Qb + k - wf] = b >= 0 ? g.tb[(int64_t)b * g.Qb + k - wf] : 0.0;
   }
   if (!g.fover && !g.u0) return;
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < g.Bs * g.Nm; idx += stride) {

@@ -958,7 +958,7 @@ int rb_solve_uneven(rb_ctx* c, int set, int B, const int* Nd, int ldu, const dou
   Workspace* w;
   if (int rc = workspace(c, stream, off, &w)) return rc;
   char* base = (char*)w->buf.p;
-  rb::UnevenIo io;
+  rb::UnevenIo io{};
   io.Bs = Bs; io.nbad = nbad; io.perm = (const int*)(base + o_perm);
   io.Q = s->Q; io.Qc = s->Qc; io.Qf = s->Qf; io.Nm = Nm; io.ldu = ldu;
   io.ta = ta; io.tc = tc; io.tf = tf; io.fover = fover; io.u0 = u0;
@@ -1121,6 +1121,107 @@ int rb_recover_pressure(rb_ctx* c, int set, int B, int N, int Np, int ldu, int l
   if (int rc = workspace(c, stream, pressure_bytes(B, N, Np), &w)) return rc;
   return enqueue_pressure(c, s, B, N, Np, ldu, ldp, ta, tc, tf, tb, u, p, status,
                           (char*)w->buf.p, (hipStream_t)stream);
+}
+
+int rb_recover_pressure_uneven(rb_ctx* c, int set, int B, const int* Nd, int Np, int ldu,
+                               int ldp, const double* ta, const double* tc, const double* tf,
+                               const double* tb, const double* u, double* p, int* status,
+                               void* stream) {
+  if (!c) return fail(RB_E_INVAL, "rb_recover_pressure_uneven: NULL context");
+  Set* s = get_set(c, set);
+  if (!s) return fail(RB_E_INVAL, "rb_recover_pressure_uneven: unknown set %d", set);
+  if (s->Np == 0)
+    return fail(RB_E_INVAL, "rb_recover_pressure_uneven: set %d has no pressure data", set);
+  if (B < 0) return fail(RB_E_INVAL, "rb_recover_pressure_uneven: B=%d", B);
+  if (Np < 1 || Np > s->Np || ldu < s->N || ldp < Np)
+    return fail(RB_E_INVAL, "rb_recover_pressure_uneven: Np=%d ldu=%d ldp=%d out of range", Np,
+                ldu, ldp);
+  if (B == 0) return RB_OK;
+  if (!Nd || !ta || !tc || !tf || !tb || !u || !p || !status)
+    return fail(RB_E_INVAL, "rb_recover_pressure_uneven: NULL array");
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (int rc = use_device(c)) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  const int Nm = s->N;
+  if (int rc = ensure_pinned(c, (size_t)3 * B + 64 * 160)) return rc;
+  int* hN = c->pin;
+  HIP_TRY(hipMemcpyAsync(hN, Nd, (size_t)B * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  std::map<int, std::vector<int>, std::greater<int>> groups;
+  std::vector<int> bad;
+  for (int b = 0; b < B; ++b) {
+    const int n = hN[b];
+    if (n < 1 || n > Nm) bad.push_back(b);
+    else groups[n].push_back(b);
+  }
+  struct Group { int N; int64_t cnt, Bp, off; size_t part; };
+  std::vector<Group> gs;
+  int64_t Bs = 0;
+  for (auto& kv : groups) {
+    Group g;
+    g.N = kv.first;
+    g.cnt = (int64_t)kv.second.size();
+    g.Bp = ceil_to(g.cnt, rb::kTile);
+    g.off = Bs;
+    Bs += g.Bp;
+    gs.push_back(g);
+  }
+  const int nbad = (int)bad.size();
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o2 = off;
+    off += (size_t)ceil_to((int64_t)bytes, 256);
+    return o2;
+  };
+  const size_t o_ta = take(Bs * s->Q * 8), o_tc = take(Bs * s->Qc * 8), o_tf = take(Bs * s->Qf * 8);
+  const size_t o_tb = take(Bs * s->Qb * 8), o_u = take(Bs * Nm * 8), o_p = take(Bs * Np * 8);
+  const size_t o_st = take(Bs * 4), o_dummy = take((size_t)B * 4), o_perm = take((Bs + nbad) * 4);
+  for (auto& g : gs) g.part = take(pressure_bytes((int)g.cnt, g.N, Np));
+  Workspace* w;
+  if (int rc = workspace(c, stream, off, &w)) return rc;
+  char* base = (char*)w->buf.p;
+  int* hp = c->pin + B;
+  {
+    int64_t r = 0;
+    for (auto& g : gs) {
+      const auto& src = groups[g.N];
+      for (int64_t k = 0; k < g.Bp; ++k) hp[r++] = k < g.cnt ? src[k] : -1;
+    }
+    for (int b : bad) hp[r++] = b;
+  }
+  HIP_TRY(hipMemcpyAsync(base + o_perm, hp, (size_t)(Bs + nbad) * sizeof(int),
+                         hipMemcpyHostToDevice, st));
+  // gather theta and u (into the u0 staging slot) in group order
+  rb::UnevenIo io{};
+  io.Bs = Bs; io.nbad = nbad; io.perm = (const int*)(base + o_perm);
+  io.Q = s->Q; io.Qc = s->Qc; io.Qf = s->Qf; io.Nm = Nm; io.ldu = ldu;
+  io.ta = ta; io.tc = tc; io.tf = tf; io.fover = nullptr; io.u0 = u;
+  io.ta_s = (double*)(base + o_ta); io.tc_s = (double*)(base + o_tc);
+  io.f_s = (double*)(base + o_tf); io.u0_s = (double*)(base + o_u);
+  io.tb = tb; io.tb_s = (double*)(base + o_tb); io.Qb = s->Qb;
+  if (Bs > 0)
+    hipLaunchKernelGGL(rb::uneven_gather_kernel, dim3(launch_grid(Bs * Nm)), dim3(256), 0, st, io);
+  HIP_TRY(hipGetLastError());
+  double* p_s = (double*)(base + o_p);
+  int* st_s = (int*)(base + o_st);
+  for (auto& g : gs) {
+    const int64_t r0 = g.off;
+    if (int rc = enqueue_pressure(c, s, (int)g.cnt, g.N, Np, Nm, Np, io.ta_s + r0 * s->Q,
+                                  io.tc_s + r0 * s->Qc, io.f_s + r0 * s->Qf,
+                                  io.tb_s + r0 * s->Qb, io.u0_s + r0 * Nm, p_s + r0 * Np,
+                                  st_s + r0, base + g.part, st))
+      return rc;
+  }
+  // scatter p and the statuses back (rows of length Np, caller stride ldp)
+  rb::UnevenIo so{};
+  so.Bs = Bs; so.nbad = nbad; so.perm = io.perm;
+  so.Nm = Np; so.ldu = ldp;
+  so.u_s = p_s; so.it_s = st_s; so.st_s = st_s;
+  so.u = p; so.iters = (int*)(base + o_dummy); so.status = status;
+  hipLaunchKernelGGL(rb::uneven_scatter_kernel, dim3(launch_grid((Bs + nbad) * ldp)), dim3(256),
+                     0, st, so);
+  HIP_TRY(hipGetLastError());
+  return RB_OK;
 }
 
 int rb_timing_enable(rb_ctx* c, int enable) {

@@ -20,7 +20,7 @@ RB_PREC_F64, RB_PREC_F32, RB_PREC_BF16 = 0, 1, 2
 
 EXPORTED = ("rb_create", "rb_destroy", "rb_last_error", "rb_hbm_used", "rb_load_tensors",
             "rb_theta", "rb_solve_batch", "rb_solve_uneven", "rb_autotune", "rb_tuned_config",
-            "rb_recover_pressure", "rb_server_start", "rb_server_submit", "rb_server_poll",
+            "rb_recover_pressure", "rb_recover_pressure_uneven", "rb_server_start", "rb_server_submit", "rb_server_poll",
             "rb_server_stats", "rb_server_stop", "rb_timing_enable", "rb_timing_read")
 RB_ST_FAILED = 5
 RB_MAX_N, RB_MAX_NP = 152, 64
@@ -102,6 +102,8 @@ def load(path=None):
     lib.rb_tuned_config.argtypes = [_vp, ct.c_int, ct.c_int, ct.c_int, ct.c_int,
                                     ct.POINTER(ct.c_int), ct.POINTER(ct.c_int)]
     lib.rb_recover_pressure.argtypes = ([_vp] + [ct.c_int] * 6 + [_vp] * 7 + [_vp])
+    lib.rb_recover_pressure_uneven.argtypes = ([_vp, ct.c_int, ct.c_int, _vp] + [ct.c_int] * 3 +
+                                               [_vp] * 7 + [_vp])
     lib.rb_server_start.argtypes = [_vp, ct.c_int, ct.POINTER(ServerOpts), ct.POINTER(_vp)]
     lib.rb_server_submit.argtypes = [_vp, ct.POINTER(Request), ct.c_int,
                                      ct.POINTER(ct.c_longlong)]
@@ -229,6 +231,14 @@ def rb_recover_pressure(ctx, set_id, B, N, Np, ldu, ldp, theta_a, theta_c, theta
                                       _stream(stream)))
 
 
+def rb_recover_pressure_uneven(ctx, set_id, B, N, Np, ldu, ldp, theta_a, theta_c, theta_f,
+                               theta_b, u, p, status, stream=None):
+    _check(load().rb_recover_pressure_uneven(ctx, set_id, int(B), _ptr(N), int(Np), int(ldu),
+                                             int(ldp), _ptr(theta_a), _ptr(theta_c),
+                                             _ptr(theta_f), _ptr(theta_b), _ptr(u), _ptr(p),
+                                             _ptr(status), _stream(stream)))
+
+
 def rb_timing_enable(ctx, enable=True):
     _check(load().rb_timing_enable(ctx, int(bool(enable))))
 
@@ -302,6 +312,18 @@ class Solver:
         opts = make_opts(tol, max_iter, precision, refine_steps)
         rb_solve_uneven(self.ctx, self.set, B, Nreq, self.N, th["ta"], th["tc"], th["tf"],
                         f_override, u0, opts, out["u"], out["iters"], out["status"], stream)
+        return out
+
+    def pressure_uneven(self, th, u, Nreq, Np=None, out=None, stream=None):
+        t = self.torch
+        Np = self.Np if Np is None else Np
+        B = u.shape[0]
+        if out is None:
+            out = dict(p=t.empty(B, self.Np, dtype=t.float64, device=self.dev),
+                       pstatus=t.empty(B, dtype=t.int32, device=self.dev))
+        rb_recover_pressure_uneven(self.ctx, self.set, B, Nreq, Np, u.shape[1], self.Np,
+                                   th["ta"], th["tc"], th["tf"], th["tb"], u, out["p"],
+                                   out["pstatus"], stream)
         return out
 
     def autotune(self, th, N=None, tol=1e-12, max_iter=10, precision=RB_PREC_F64,

@@ -103,6 +103,38 @@ def test_uneven_fp64_matches_oracle(oracle_lib, R, c2):
     s.close()
 
 
+def test_uneven_pressure_matches_oracle(oracle_lib, R, c2):
+    """Velocity and pressure of a mixed-N batch, each request at its own N."""
+    O = oracle_lib
+    cfg = get_config("batched_n50")
+    rng = np.random.default_rng(8)
+    Nreq = rng.choice(np.array([3, 17, 30, 50], np.int32), size=261)
+    Nreq[5] = 0                                     # invalid size: status 4, p = 0
+    mu = draw_mu(cfg, 261, seed_offset=12)
+    s = R.Solver(c2)
+    th = s.theta(_dev(mu))
+    Nd = _dev(Nreq, torch.int32)
+    out = s.solve_uneven(th, Nd)
+    pr = s.pressure_uneven(th, out["u"], Nd)
+    torch.cuda.synchronize()
+    ok = Nreq > 0
+    r = O.solve_batch(O.OracleSet(c2), mu[ok], Nreq=Nreq[ok], pressure_np=c2.Np)
+    ps = pr["pstatus"].cpu().numpy()
+    pg = pr["p"].cpu().numpy()
+    assert ps[5] == R.RB_ST_BADN and not np.any(pg[5])
+    assert np.all(ps[ok] == 0)
+    assert np.max(_rel(pg[ok], r["p"])) <= 1e-10
+    # the same requests through the same-N entry point
+    for n in (17, 50):
+        idx = np.nonzero(Nreq == n)[0]
+        sel = torch.as_tensor(idx, device="cuda")
+        thn = {k: v[sel] for k, v in th.items() if v is not None}
+        p1 = s.pressure(thn, out["u"][sel], N=n)
+        torch.cuda.synchronize()
+        assert np.max(_rel(pg[idx], p1["p"].cpu().numpy())) <= 1e-13
+    s.close()
+
+
 def test_uneven_bad_sizes_and_empty_groups(R, c2):
     cfg = get_config("batched_n50")
     Nreq = np.array([50, 0, -3, 51, 20, 50], np.int32)
