@@ -9,7 +9,8 @@ MFMA, pivoted LU, update, stopping test) and the a posteriori pressure recovery.
 
 Besides the batched FP64 headline (`value`), the JSON line carries, on the same N = 50
 tensor set and parameters: the plain per-solve GPU path (the same library, one request per
-call), the mixed-precision batched path (BF16 tensors on MFMA + FP64-residual refinement),
+call), the mixed-precision batched path (BF16 hi/lo tensors on MFMA + one FP64-residual
+refinement step; --mixed-prec bf16 for plain BF16 tensors and three steps),
 and the continuous-batching server under Poisson arrivals (throughput, p50/p99 latency);
 each with its maximum relative error against the FP64 oracle on a checked sample.
 Progress goes to stderr.
@@ -77,7 +78,8 @@ def other_workload(args):
     """The other synthetic workloads, each timed the same way (inputs resident, HIP-event
     kernel timing, oracle check on a sample):
       single_n10      the plain single solve (B = 1 per call, FP64)
-      mixed_n100      B = 32768 at N = 100: BF16 tensors, FP32 LU, FP64-residual refinement
+      mixed_n100      B = 32768 at N = 100: BF16 hi/lo tensors (--mixed-prec), FP32 LU, one
+                      FP64-residual refinement step
       uneven_n20_100  B = 16384 with N in {20,...,100} in one call (FP32 + refinement)
       serve_n150      the server under Poisson arrivals, N ~ U{20..150}, FP32 + refinement
     """
@@ -132,15 +134,19 @@ def other_workload(args):
         el, fams = timed(step, max(args.steps, 200), args.warmup)
         n = max(args.steps, 200)
         value, steps = n / el, n
+        ms_step = 1e3 * el / n
         r = oracle.solve_batch(oracle.OracleSet(ts), mu_h[:1], pressure_np=ts.Np)
         extra["max_rel_err_u"] = float(rel_err(out["u"].cpu().numpy(), r["u"]).max())
         extra["max_rel_err_p"] = float(rel_err(pout["p"].cpu().numpy(), r["p"]).max())
         extra["mean_ms_per_solve"] = 1e3 * el / n
     elif name in ("mixed_n100", "uneven_n20_100"):
         uneven = name == "uneven_n20_100"
-        prec = rbns.RB_PREC_F32 if uneven else rbns.RB_PREC_BF16
-        refine = 2 if uneven else args.mixed_refine if args.mixed_refine >= 0 else 3
-        dtype = "f32" if uneven else "bf16"
+        x3 = args.mixed_prec == "bf16x3"
+        prec = (rbns.RB_PREC_F32 if uneven else
+                rbns.RB_PREC_BF16X3 if x3 else rbns.RB_PREC_BF16)
+        refine = (2 if uneven else args.mixed_refine if args.mixed_refine >= 0 else
+                  1 if x3 else 3)
+        dtype = "f32" if uneven else args.mixed_prec
         Nreq = draw_basis_sizes(cfg, B) if uneven else np.full(B, ts.N, np.int32)
         Nd = torch.as_tensor(Nreq, device=dev, dtype=torch.int32)
         out = dict(u=torch.empty(B, ts.N, **f64), iters=torch.empty(B, dtype=torch.int32, device=dev),
@@ -159,10 +165,11 @@ def other_workload(args):
         nsteps = max(3, args.steps // 4)
         el, fams = timed(step, nsteps, max(2, args.warmup // 2))
         value, steps = B * nsteps / el, nsteps
+        ms_step = 1e3 * el / nsteps
         metric = ("reduced NS solves/sec, uneven N in {20..100} in one call (FP32 + FP64 "
                   "refinement)" if uneven else
-                  "reduced NS solves/sec at N=100 (BF16 MFMA + FP64-residual refinement, "
-                  "velocity + pressure)")
+                  f"reduced NS solves/sec at N=100 ({args.mixed_prec.upper()} MFMA + "
+                  f"{refine} FP64-residual refinement step(s), velocity + pressure)")
         idx = np.linspace(0, B - 1, max(args.check, 1)).astype(int)
         r = oracle.solve_batch(oracle.OracleSet(ts), mu_h[idx], Nreq=Nreq[idx],
                                pressure_np=0 if uneven else ts.Np)
@@ -177,7 +184,8 @@ def other_workload(args):
         its = out["iters"].cpu().numpy().astype(float)
         jac_flops = float((2.0 * Nreq ** 2 * K * np.maximum(its - refine, 1)).sum()) * nsteps
         res_flops = float((2.0 * Nreq ** 2 * K * refine).sum()) * nsteps
-        peak_j = 2516.6 if prec == rbns.RB_PREC_BF16 else 157.3
+        # algorithmic flops (BF16x3 issues three MFMAs per product) against the dense peak
+        peak_j = 157.3 if prec == rbns.RB_PREC_F32 else 2516.6
         kern = {}
         for f, (ms, n) in fams.items():
             kern[f] = dict(total_ms=ms, launches=n)
@@ -249,6 +257,7 @@ def other_workload(args):
             srv.stop()
         top = served[f"{int(rates[-1])}"]
         value, steps = top["value"], len(rates)
+        ms_step = None                            # open-loop serving: no step
         extra["served"] = served
         extra["p99_ms"] = top["p99_ms"]
         fams = {}
@@ -256,7 +265,7 @@ def other_workload(args):
         raise SystemExit(f"unknown workload {name}")
 
     res = {"metric": metric, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": steps,
-           "warmup": args.warmup, "ms_per_step": None, "higher_is_better": True,
+           "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic",
            "config": {"workload": name, "N": ts.N, "B": B, "Q": ts.Q, "Qc": ts.Qc,
                       "parallelism": "single_gpu"},
@@ -276,8 +285,11 @@ def main():
     ap.add_argument("--plain", type=int, default=256,
                     help="requests timed on the plain one-request-per-call path (0 = skip)")
     ap.add_argument("--check", type=int, default=64, help="requests re-solved by the oracle")
-    ap.add_argument("--mixed-refine", type=int, default=3,
-                    help="refinement steps of the BF16 mixed-precision leg (-1 = skip)")
+    ap.add_argument("--mixed-refine", type=int, default=-2,
+                    help="refinement steps of the mixed-precision leg (-1 = skip; default "
+                         "1 for bf16x3, 3 for bf16)")
+    ap.add_argument("--mixed-prec", choices=("bf16x3", "bf16"), default="bf16x3",
+                    help="tensor format of the mixed-precision leg / workload")
     ap.add_argument("--serve-rates", default="200000,1000000",
                     help="Poisson arrival rates (req/s) of the serving leg ('' = skip)")
     ap.add_argument("--serve-seconds", type=float, default=1.5)
@@ -423,6 +435,9 @@ def main():
         log(f"[bench] plain path: {extra['plain']['value']:.4g} solves/s")
 
     # ---- mixed precision: BF16 tensors on MFMA, FP32 LU, FP64-residual refinement ----------
+    mprec = rbns.RB_PREC_BF16X3 if args.mixed_prec == "bf16x3" else rbns.RB_PREC_BF16
+    if args.mixed_refine == -2:
+        args.mixed_refine = 1 if args.mixed_prec == "bf16x3" else 3
     if args.mixed_refine >= 0:
         mo = dict(u=torch.empty(B, N, **f64), iters=torch.empty(B, dtype=torch.int32, device=dev),
                   status=torch.empty(B, dtype=torch.int32, device=dev))
@@ -430,7 +445,7 @@ def main():
         def mstep():
             rbns.rb_theta(s.ctx, s.set, B, mu, th["ta"], th["tc"], th["tf"], th["tb"], stream)
             s.solve(th, out=mo, tol=cfg["tol"], max_iter=cfg["max_iter"],
-                    precision=rbns.RB_PREC_BF16, refine_steps=args.mixed_refine, stream=stream)
+                    precision=mprec, refine_steps=args.mixed_refine, stream=stream)
             s.pressure(th, mo["u"], out=pout, stream=stream)
         for _ in range(2):
             mstep()
@@ -442,13 +457,15 @@ def main():
         torch.cuda.synchronize()
         tm1 = time.perf_counter()
         mix = dict(value=B * nm / (tm1 - tm0), unit="solves/s", refine_steps=args.mixed_refine,
-                   dtype="bf16 tensors / fp32 accumulate + lu / fp64 residual and iterate",
+                   dtype=f"{args.mixed_prec} tensors / fp32 accumulate + lu / fp64 residual "
+                         "and iterate",
                    status_hist=np.bincount(mo["status"].cpu().numpy(), minlength=5).tolist())
         if ref is not None:
             mix["max_rel_err_u"] = float(rel_err(mo["u"].cpu().numpy()[idx], ref["u"]).max())
             mix["max_rel_err_p"] = float(rel_err(pout["p"].cpu().numpy()[idx], ref["p"]).max())
-        extra["mixed_bf16"] = mix
-        log(f"[bench] mixed BF16 + {args.mixed_refine} refinement steps: {mix['value']:.4g} solves/s")
+        extra["mixed_" + args.mixed_prec] = mix
+        log(f"[bench] mixed {args.mixed_prec} + {args.mixed_refine} refinement steps: "
+            f"{mix['value']:.4g} solves/s")
 
     # ---- served: continuous batching under Poisson arrivals --------------------------------
     rates = [float(r) for r in args.serve_rates.split(",") if r.strip()]

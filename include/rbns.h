@@ -53,6 +53,9 @@ extern "C" {
 #define RB_PREC_F32      1    /* FP32 tensors + FP32 MFMA contraction, FP32 LU, FP64 iterates,
                                  then FP64-residual refinement steps                          */
 #define RB_PREC_BF16     2    /* as RB_PREC_F32 with BF16 tensors on BF16 MFMA (FP32 accum.) */
+#define RB_PREC_BF16X3   3    /* as RB_PREC_BF16 with tensors and iterate terms each split into
+                                 a BF16 high and low part, three BF16 MFMAs per product (about
+                                 16 mantissa bits), so one refinement step reaches ~1e-9       */
 
 typedef struct rb_ctx rb_ctx;
 
@@ -147,9 +150,10 @@ int rb_theta(rb_ctx *ctx, int set, int B, const double *mu, double *theta_a, dou
  * Device outputs: u [B][ldu] (entries >= N are set to 0), iters [B] (Newton updates applied),
  * status [B] (RB_ST_*). ldu >= N is the row stride of u0 / f_override / u.
  * opts == NULL selects tol 1e-12, max_iter 10, RB_PREC_F64.
- * Mixed precisions (RB_PREC_F32 / RB_PREC_BF16): the low-precision phase stops a request when
- * its update is below tol or has stagnated (update <= 1e-3 ||u|| for FP32, 5e-2 ||u|| for BF16,
- * and no longer halving), or at max_iter. Then every request without a failure status takes
+ * Mixed precisions (RB_PREC_F32 / RB_PREC_BF16 / RB_PREC_BF16X3): the low-precision phase stops
+ * a request when its update is below tol or has stagnated (update <= 5e-2 ||u|| for BF16,
+ * 1e-3 ||u|| for the others, and no longer halving), or at max_iter. RB_PREC_BF16X3 needs
+ * Qc*N <= 640, RB_PREC_BF16 likewise. Then every request without a failure status takes
  * up to refine_steps refinement steps (FP64 residual, the Jacobian of its last low-precision
  * step) until an update is below tol (status RB_ST_CONVERGED, else RB_ST_MAXIT). iters
  * counts both kinds of updates.

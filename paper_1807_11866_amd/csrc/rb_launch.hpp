@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include "rb_lowprec.hpp"
+#include "rbns.h"
 
 namespace rb {
 namespace launch {
@@ -17,8 +18,9 @@ int contract_f64(int mode, const ContractArgs& g, hipStream_t st);
 // workgroup per system.
 int lu_f64(int NP, const NewtonF64Args& a, int it, bool lds_bcast, hipStream_t st);
 int plu_f64(int NPP, const PressureF64Args& a, bool lds_bcast, hipStream_t st);
-// Low-precision contraction: BF16 KT <= 20; FP32 KT even <= 64 or a multiple of 4 <= 152.
-int contract_lp(bool bf16, int KT, const ContractLpArgs& g, hipStream_t st);
+// Low-precision contraction, prec = RB_PREC_F32 (KT even <= 64 or a multiple of 4 <= 152),
+// RB_PREC_BF16 (KT <= 20) or RB_PREC_BF16X3 (KT <= 20).
+int contract_lp(int prec, int KT, const ContractLpArgs& g, hipStream_t st);
 // FP32 LU of the mixed-precision Newton: NP <= 64 or a multiple of 8 <= 152.
 int lu_lp(int NP, bool refine, const LpNewtonArgs& a, int it, hipStream_t st);
 
@@ -30,6 +32,7 @@ int lu_f64_mw(int NP, const NewtonF64Args& a, int it, hipStream_t st);
 int lu_lp_mw(int NP, bool refine, const LpNewtonArgs& a, int it, hipStream_t st);
 int lu_lp_mw_wide(int NP, bool refine, const LpNewtonArgs& a, int it, hipStream_t st);
 int contract_lp_f32_wide(int KT, const ContractLpArgs& g, hipStream_t st);
+int contract_lp_bf16x3(int KT, const ContractLpArgs& g, hipStream_t st);
 
 }  // namespace launch
 }  // namespace rb

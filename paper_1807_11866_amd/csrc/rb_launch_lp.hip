@@ -1,5 +1,5 @@
 // Instantiations of the mixed-precision contraction: BF16 per tensor length KT <= 20, FP32 per
-// even KT <= 64 (longer FP32 tensor parts: rb_launch_lp_wide.hip).
+// even KT <= 64 (longer FP32 tensor parts: rb_launch_lp_wide.hip; BF16x3: rb_launch_lp_x3.hip).
 #include "rb_launch.hpp"
 
 namespace rb {
@@ -17,8 +17,9 @@ static int go_c(const ContractLpArgs& g, hipStream_t st) {
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
-int contract_lp(bool bf16, int KT, const ContractLpArgs& g, hipStream_t st) {
-  if (bf16) {
+int contract_lp(int prec, int KT, const ContractLpArgs& g, hipStream_t st) {
+  if (prec == RB_PREC_BF16X3) return contract_lp_bf16x3(KT, g, st);
+  if (prec == RB_PREC_BF16) {
     switch (KT) {
 #define RB_KT(n) case n: return go_c<true, n>(g, st);
       RB_KT(1) RB_KT(2) RB_KT(3) RB_KT(4) RB_KT(5) RB_KT(6) RB_KT(7) RB_KT(8) RB_KT(9) RB_KT(10)

@@ -42,7 +42,16 @@ __host__ __device__ inline uint16_t f64_to_bf16(double x) {
 //   BF16 (v_mfma_f32_16x16x32_bf16): tile (rb, ks) = 64 lanes x 8 bf16, lane e holds row
 //        rb*16 + e%16, k = ks*32 + 8*(e/16) + t (t = 0..7); affine part 1 k-step (Q <= 32),
 //        tensor part KT = ceil(Qc*N/32) k-steps.
-template <bool kBF16>
+//   BF16x3 (kSplit3): the BF16 layout twice, hi = bf16(v) then lo = bf16(v - hi) at out + total
+//        (a 16-bit-mantissa representation of v as the sum of two BF16 numbers).
+__host__ __device__ inline double bf16_to_f64(uint16_t h) {
+  const uint32_t u = static_cast<uint32_t>(h) << 16;
+  float f;
+  __builtin_memcpy(&f, &u, 4);
+  return static_cast<double>(f);
+}
+
+template <bool kBF16, bool kSplit3 = false>
 __global__ void pack_lp(const double* __restrict__ C, const double* __restrict__ A, int Nm, int N,
                         int Q, int Qc, int kA, int nrb, int nks, void* __restrict__ out) {
   constexpr int kK = kBF16 ? 32 : 4;        // k per k-step
@@ -73,15 +82,19 @@ __global__ void pack_lp(const double* __restrict__ C, const double* __restrict__
         v = C[(((int64_t)q * Nm + i) * Nm + j) * Nm + l] + C[(((int64_t)q * Nm + i) * Nm + l) * Nm + j];
       }
     }
-    if (kBF16)
-      static_cast<uint16_t*>(out)[idx] = f64_to_bf16(v);
-    else
+    if (kBF16) {
+      const uint16_t hi = f64_to_bf16(v);
+      static_cast<uint16_t*>(out)[idx] = hi;
+      if (kSplit3) static_cast<uint16_t*>(out)[total + idx] = f64_to_bf16(v - bf16_to_f64(hi));
+    } else {
       static_cast<float*>(out)[idx] = static_cast<float>(v);
+    }
   }
 }
 
 struct ContractLpArgs {
   const void* op;          // packed operand (float or bf16)
+  const void* op_lo;       // BF16x3: the low parts (same layout), else nullptr
   int nrb, kA, nks;        // row blocks, affine k-steps, k-steps per row block
   int N, M, Q, Qc, B;
   int64_t Bp;
@@ -104,9 +117,10 @@ __host__ __device__ inline int64_t contract_lp_lds_bytes(int N) {
 // Same decomposition as contract_f64_kernel (64-request tile x row split per workgroup,
 // 16 requests and their W slice per wavefront, four row blocks per pass, static prefetch),
 // with FP32 (or BF16) operands and FP32 accumulators; the whole tensor part (KT k-steps) is
-// one chunk. Accumulator layout of the 16x16 FP32 MFMAs: lane l, element v = row
-// 4*(l/16) + v, column l%16.
-template <bool kBF16, int KT>
+// one chunk. kS3 (BF16x3): operand and W are both split into hi + lo BF16 parts and every
+// product is hi*hi + hi*lo + lo*hi (three MFMAs, about 16 mantissa bits). Accumulator layout
+// of the 16x16 FP32 MFMAs: lane l, element v = row 4*(l/16) + v, column l%16.
+template <bool kBF16, int KT, bool kS3 = false>
 __global__ __launch_bounds__(kThreads) void contract_lp_kernel(ContractLpArgs a) {
   extern __shared__ float smemf[];
   typedef typename std::conditional<kBF16, bf16x8, float>::type opnd;
@@ -152,43 +166,64 @@ __global__ __launch_bounds__(kThreads) void contract_lp_kernel(ContractLpArgs a)
     for (int qq = 0; qq < kMaxQc; ++qq) tq = (q == qq) ? tcv[qq] : tq;
     return q < kMaxQc ? tq * ul[bl * N + l] : 0.f;
   };
-  opnd wA[kAmax], wT[KT];
-  auto make = [&](int ks) -> opnd {
+  constexpr int kP = kS3 ? 2 : 1;           // hi (and lo) parts
+  opnd wA[kP][kAmax], wT[kP][KT];
+  auto make = [&](int ks, opnd (&dst)[kP]) {
     if constexpr (kBF16) {
-      bf16x8 r;
 #pragma unroll
-      for (int t = 0; t < 8; ++t)
-        r[t] = static_cast<short>(f64_to_bf16(static_cast<double>(wval(ks * kK + 8 * (lane >> 4) + t))));
-      return r;
+      for (int t = 0; t < 8; ++t) {
+        const double v = static_cast<double>(wval(ks * kK + 8 * (lane >> 4) + t));
+        const uint16_t hi = f64_to_bf16(v);
+        dst[0][t] = static_cast<short>(hi);
+        if constexpr (kS3) dst[kP - 1][t] = static_cast<short>(f64_to_bf16(v - bf16_to_f64(hi)));
+      }
     } else {
-      return wval(ks * kK + (lane >> 4));
+      dst[0] = wval(ks * kK + (lane >> 4));
     }
   };
 #pragma unroll
-  for (int ks = 0; ks < kAmax; ++ks) wA[ks] = make(ks);
+  for (int ks = 0; ks < kAmax; ++ks) {
+    opnd tmp[kP];
+    make(ks, tmp);
 #pragma unroll
-  for (int ks = 0; ks < KT; ++ks) wT[ks] = make(a.kA + ks);
+    for (int pp = 0; pp < kP; ++pp) wA[pp][ks] = tmp[pp];
+  }
+#pragma unroll
+  for (int ks = 0; ks < KT; ++ks) {
+    opnd tmp[kP];
+    make(a.kA + ks, tmp);
+#pragma unroll
+    for (int pp = 0; pp < kP; ++pp) wT[pp][ks] = tmp[pp];
+  }
 
   const int rb_lo = (int)((int64_t)split * a.nrb / a.nsplit);
   const int rb_hi = (int)((int64_t)(split + 1) * a.nrb / a.nsplit);
   const int col = bl;
-  const opnd* opb = static_cast<const opnd*>(a.op);
+  const opnd* opb[kP];
+  opb[0] = static_cast<const opnd*>(a.op);
+  if constexpr (kS3) opb[kP - 1] = static_cast<const opnd*>(a.op_lo);
 
   for (int g0 = rb_lo; g0 < rb_hi; g0 += kGroup) {
-    const opnd* opg[kGroup];
+    const opnd* opg[kP][kGroup];
 #pragma unroll
-    for (int r = 0; r < kGroup; ++r)
-      opg[r] = opb + (int64_t)min(g0 + r, rb_hi - 1) * a.nks * 64 + lane;
-    opnd xa[kAmax][kGroup];
+    for (int pp = 0; pp < kP; ++pp)
 #pragma unroll
-    for (int ks = 0; ks < kAmax; ++ks)
+      for (int r = 0; r < kGroup; ++r)
+        opg[pp][r] = opb[pp] + (int64_t)min(g0 + r, rb_hi - 1) * a.nks * 64 + lane;
+    opnd xa[kP][kAmax][kGroup];
 #pragma unroll
-      for (int r = 0; r < kGroup; ++r) xa[ks][r] = opg[r][min(ks, a.kA - 1) * 64];
-    opnd x[KT][kGroup];
+    for (int pp = 0; pp < kP; ++pp)
+#pragma unroll
+      for (int ks = 0; ks < kAmax; ++ks)
+#pragma unroll
+        for (int r = 0; r < kGroup; ++r) xa[pp][ks][r] = opg[pp][r][min(ks, a.kA - 1) * 64];
+    opnd x[kP][KT][kGroup];
 #pragma unroll
     for (int ks = 0; ks < kDepth && ks < KT; ++ks)
 #pragma unroll
-      for (int r = 0; r < kGroup; ++r) x[ks][r] = opg[r][(a.kA + ks) * 64];
+      for (int pp = 0; pp < kP; ++pp)
+#pragma unroll
+        for (int r = 0; r < kGroup; ++r) x[pp][ks][r] = opg[pp][r][(a.kA + ks) * 64];
 
     auto mfma = [](opnd xx, opnd ww, f32x4 cc) -> f32x4 {
       if constexpr (kBF16)
@@ -199,11 +234,25 @@ __global__ __launch_bounds__(kThreads) void contract_lp_kernel(ContractLpArgs a)
     f32x4 c[kGroup];
 #pragma unroll
     for (int r = 0; r < kGroup; ++r) c[r] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // hi*hi (+ hi*lo + lo*hi for BF16x3)
+    auto mac = [&](const opnd (&xx)[kP], const opnd (&ww)[kP], f32x4 cc) -> f32x4 {
+      cc = mfma(xx[0], ww[0], cc);
+      if constexpr (kS3) {
+        cc = mfma(xx[0], ww[kP - 1], cc);
+        cc = mfma(xx[kP - 1], ww[0], cc);
+      }
+      return cc;
+    };
 #pragma unroll
     for (int ks = 0; ks < kAmax; ++ks) {
       if (ks < a.kA) {
 #pragma unroll
-        for (int r = 0; r < kGroup; ++r) c[r] = mfma(xa[ks][r], wA[ks], c[r]);
+        for (int r = 0; r < kGroup; ++r) {
+          opnd xx[kP], ww[kP];
+#pragma unroll
+          for (int pp = 0; pp < kP; ++pp) { xx[pp] = xa[pp][ks][r]; ww[pp] = wA[pp][ks]; }
+          c[r] = mac(xx, ww, c[r]);
+        }
       }
     }
     // fold A(mu) rows: acc[m] * u_j into p_i (m = j*N + i)
@@ -226,10 +275,18 @@ __global__ __launch_bounds__(kThreads) void contract_lp_kernel(ContractLpArgs a)
     for (int ks = 0; ks < KT; ++ks) {
       if (ks + kDepth < KT) {
 #pragma unroll
-        for (int r = 0; r < kGroup; ++r) x[ks + kDepth][r] = opg[r][(a.kA + ks + kDepth) * 64];
+        for (int pp = 0; pp < kP; ++pp)
+#pragma unroll
+          for (int r = 0; r < kGroup; ++r)
+            x[pp][ks + kDepth][r] = opg[pp][r][(a.kA + ks + kDepth) * 64];
       }
 #pragma unroll
-      for (int r = 0; r < kGroup; ++r) c[r] = mfma(x[ks][r], wT[ks], c[r]);
+      for (int r = 0; r < kGroup; ++r) {
+        opnd xx[kP], ww[kP];
+#pragma unroll
+        for (int pp = 0; pp < kP; ++pp) { xx[pp] = x[pp][ks][r]; ww[pp] = wT[pp][ks]; }
+        c[r] = mac(xx, ww, c[r]);
+      }
     }
 #pragma unroll
     for (int r = 0; r < kGroup; ++r) {

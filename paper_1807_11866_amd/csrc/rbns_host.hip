@@ -52,6 +52,7 @@ struct DevBuf {
 
 struct Pack {              // packed MFMA operand for one basis size
   DevBuf buf;
+  const void* lo = nullptr;  // BF16x3: low parts (inside buf)
   int nrb = 0, nks_s = 0, nks = 0;
   int nchunk = 1;          // tensor part = nchunk chunks of (nks - nks_s) / nchunk k-steps
 };
@@ -62,7 +63,7 @@ struct Set {
   bool hasH = false;
   std::map<int, Pack> solve_f64;                     // key: N
   std::map<std::pair<int, int>, Pack> press_f64;     // key: (N, Np)
-  std::map<std::pair<int, int>, Pack> solve_lp;      // key: (N, 0 = FP32 | 1 = BF16)
+  std::map<std::pair<int, int>, Pack> solve_lp;      // key: (N, RB_PREC_*)
 };
 
 struct Workspace {
@@ -220,8 +221,8 @@ int press_pack_f64(rb_ctx* c, Set* s, int N, int Np, Pack** out) {
   return RB_OK;
 }
 
-// Mixed-precision packed operand for basis size N (FP32 or BF16 copy of the FP64 tensors).
-// FP32: ceil(Qc*N/4) k-steps rounded up to even (to a multiple of 4 beyond 64); BF16:
+// Mixed-precision packed operand for basis size N (FP32, BF16 or BF16 hi + lo copy of the FP64
+// tensors). FP32: ceil(Qc*N/4) k-steps rounded up to even (to a multiple of 4 beyond 64); BF16:
 // ceil(Qc*N/32) k-steps of 32. The whole tensor part is held in registers.
 int lp_tensor_ksteps(int Qc, int N, bool bf16) {
   if (bf16) return (int)(ceil_to((int64_t)Qc * N, 32) / 32);
@@ -229,8 +230,9 @@ int lp_tensor_ksteps(int Qc, int N, bool bf16) {
   return (int)ceil_to(raw, raw > 64 ? 4 : 2);
 }
 
-int solve_pack_lp(rb_ctx* c, Set* s, int N, bool bf16, Pack** out) {
-  auto key = std::make_pair(N, bf16 ? 1 : 0);
+int solve_pack_lp(rb_ctx* c, Set* s, int N, int prec, Pack** out) {
+  const bool bf16 = prec != RB_PREC_F32, x3 = prec == RB_PREC_BF16X3;
+  auto key = std::make_pair(N, prec);
   auto it = s->solve_lp.find(key);
   if (it != s->solve_lp.end()) { *out = &it->second; return RB_OK; }
   Pack p;
@@ -238,9 +240,14 @@ int solve_pack_lp(rb_ctx* c, Set* s, int N, bool bf16, Pack** out) {
   p.nks_s = bf16 ? 1 : (s->Q + 3) / 4;
   p.nks = p.nks_s + lp_tensor_ksteps(s->Qc, N, bf16);
   const int64_t total = (int64_t)p.nrb * p.nks * 64 * (bf16 ? 8 : 1);
-  int rc = dev_alloc(c, p.buf, total * (bf16 ? 2 : 4));
+  int rc = dev_alloc(c, p.buf, total * (bf16 ? 2 : 4) * (x3 ? 2 : 1));
   if (rc) return rc;
-  if (bf16)
+  if (x3) {
+    p.lo = (const uint16_t*)p.buf.p + total;
+    hipLaunchKernelGGL((rb::pack_lp<true, true>), dim3(launch_grid(total)), dim3(256), 0, 0,
+                       (const double*)s->C.p, (const double*)s->A.p, s->N, N, s->Q, s->Qc,
+                       p.nks_s, p.nrb, p.nks, p.buf.p);
+  } else if (bf16)
     hipLaunchKernelGGL(rb::pack_lp<true>, dim3(launch_grid(total)), dim3(256), 0, 0,
                        (const double*)s->C.p, (const double*)s->A.p, s->N, N, s->Q, s->Qc,
                        p.nks_s, p.nrb, p.nks, p.buf.p);
@@ -402,17 +409,17 @@ int enqueue_newton(rb_ctx* c, const rb::NewtonF64Args& a, bool lu_lds, hipStream
   return RB_OK;
 }
 
-// Mixed-precision batched Newton: the low-precision phase (FP32 or BF16 contraction, FP32
-// LU, FP64 iterates) until each request's update is below tol or has stagnated, then up to
+// Mixed-precision batched Newton: the low-precision phase (FP32, BF16 or BF16x3 contraction,
+// FP32 LU, FP64 iterates) until each request's update is below tol or has stagnated, then up to
 // refine_steps refinement steps, each with the FP64 residual and the Jacobian of the last
 // low-precision step, until the update is below tol.
-int enqueue_newton_lp(rb_ctx* c, Set* s, const rb::NewtonF64Args& a, bool bf16, int refine,
+int enqueue_newton_lp(rb_ctx* c, Set* s, const rb::NewtonF64Args& a, int prec, int refine,
                       char* base, hipStream_t st) {
   const int N = a.N, NP = a.s.NP;
   const int64_t Bp = a.s.Bp, mp = a.s.mp;
   Pack *pf, *pl;
   if (int rc = solve_pack_f64(c, s, N, &pf)) return rc;
-  if (int rc = solve_pack_lp(c, s, N, bf16, &pl)) return rc;
+  if (int rc = solve_pack_lp(c, s, N, prec, &pl)) return rc;
   const int nsplit = a.s.nsplit;
   float* J32 = (float*)base;               // low-precision buffers (lp_extra_bytes)
   float* part32 = J32 + Bp * mp;
@@ -420,7 +427,7 @@ int enqueue_newton_lp(rb_ctx* c, Set* s, const rb::NewtonF64Args& a, bool bf16, 
   partA = (double*)(((uintptr_t)partA + 255) & ~(uintptr_t)255);
 
   rb::ContractLpArgs gl;
-  gl.op = pl->buf.p;
+  gl.op = pl->buf.p; gl.op_lo = pl->lo;
   gl.nrb = pl->nrb; gl.kA = pl->nks_s; gl.nks = pl->nks;
   gl.N = N; gl.M = N * N; gl.Q = a.Q; gl.Qc = a.Qc; gl.B = a.B; gl.Bp = Bp;
   gl.ta = a.ta; gl.tc = a.tc; gl.U = a.s.U; gl.ldU = NP;
@@ -442,7 +449,7 @@ int enqueue_newton_lp(rb_ctx* c, Set* s, const rb::NewtonF64Args& a, bool bf16, 
   rb::LpNewtonArgs la;
   la.N = N; la.Nm = a.Nm; la.B = a.B;
   la.tol = a.tol; la.H = a.H;
-  la.stag = bf16 ? 5e-2 : 1e-3;
+  la.stag = prec == RB_PREC_BF16 ? 5e-2 : 1e-3;
   la.J = J32; la.mp = mp; la.part = part32; la.partA = partA; la.nreq = a.nreq;
   la.s = a.s;
 
@@ -450,7 +457,7 @@ int enqueue_newton_lp(rb_ctx* c, Set* s, const rb::NewtonF64Args& a, bool bf16, 
   for (int it = 0; it < a.maxit; ++it) {
     {
       LaunchTimer t(c, FAM_JACOBIAN, st);
-      if (int rc = launch_rc(rb::launch::contract_lp(bf16, KT, gl, st), "lp jacobian")) return rc;
+      if (int rc = launch_rc(rb::launch::contract_lp(prec, KT, gl, st), "lp jacobian")) return rc;
     }
     LaunchTimer t(c, FAM_LU, st);
     if (int rc = launch_rc(rb::launch::lu_lp(NP, false, la, it, st), "lp lu")) return rc;
@@ -548,7 +555,8 @@ Tune tune_for(rb_ctx* c, int set, int N, int precision, int64_t Bp) {
 int check_opts(const char* fn, const rb_solve_opts& o) {
   if (!(o.tol >= 0.0) || o.max_iter < 1 || o.max_iter > 1000)
     return fail(RB_E_INVAL, "%s: bad options (tol=%g, max_iter=%d)", fn, o.tol, o.max_iter);
-  if (o.precision != RB_PREC_F64 && o.precision != RB_PREC_F32 && o.precision != RB_PREC_BF16)
+  if (o.precision != RB_PREC_F64 && o.precision != RB_PREC_F32 && o.precision != RB_PREC_BF16 &&
+      o.precision != RB_PREC_BF16X3)
     return fail(RB_E_INVAL, "%s: unknown precision %d", fn, o.precision);
   if (o.precision != RB_PREC_F64 && (o.refine_steps < 0 || o.refine_steps > 100))
     return fail(RB_E_INVAL, "%s: refine_steps=%d", fn, o.refine_steps);
@@ -580,7 +588,7 @@ int enqueue_solve(rb_ctx* c, Set* s, const rb::NewtonF64Args& a, const rb_solve_
                   const Tune& t, char* region, hipStream_t st) {
   if (o.precision == RB_PREC_F64) return enqueue_newton(c, a, t.lu_lds, st);
   char* lp = region + newton_state_bytes(a.s.Bp, a.s.NP, a.s.mp, a.s.nsplit, a.s.jslices);
-  return enqueue_newton_lp(c, s, a, o.precision == RB_PREC_BF16, o.refine_steps, lp, st);
+  return enqueue_newton_lp(c, s, a, o.precision, o.refine_steps, lp, st);
 }
 
 // Autotuner. On the batch at hand (its state region sized for region_nsplit partials), time
@@ -591,10 +599,10 @@ int autotune_batch(rb_ctx* c, Set* s, int set, rb::NewtonF64Args a, const rb_sol
                    char* region, hipStream_t st, Tune* out) {
   const int N = a.N, NP = a.s.NP;
   const int64_t Bp = a.s.Bp, mp = a.s.mp;
-  const bool lp = o.precision != RB_PREC_F64, bf16 = o.precision == RB_PREC_BF16;
+  const bool lp = o.precision != RB_PREC_F64;
   Pack* pl = nullptr;
   if (lp)
-    if (int rc = solve_pack_lp(c, s, N, bf16, &pl)) return rc;
+    if (int rc = solve_pack_lp(c, s, N, o.precision, &pl)) return rc;
   hipEvent_t e0 = take_event(c), e1 = take_event(c);
   if (!e0 || !e1) return fail(RB_E_DEVICE, "autotune: cannot create events");
   auto release = [&](int rc) {
@@ -619,13 +627,13 @@ int autotune_batch(rb_ctx* c, Set* s, int set, rb::NewtonF64Args a, const rb_sol
       return launch_rc(rb::launch::contract_f64(rb::kModeJac, g, st), "autotune contraction");
     }
     rb::ContractLpArgs g;
-    g.op = pl->buf.p;
+    g.op = pl->buf.p; g.op_lo = pl->lo;
     g.nrb = pl->nrb; g.kA = pl->nks_s; g.nks = pl->nks;
     g.N = N; g.M = N * N; g.Q = a.Q; g.Qc = a.Qc; g.B = a.B; g.Bp = Bp;
     g.ta = a.ta; g.tc = a.tc; g.U = a.s.U; g.ldU = NP;
     g.done = a.s.done; g.J = (float*)lpb; g.mp = mp;
     g.part = (float*)lpb + Bp * mp; g.ldp = NP; g.nsplit = nsplit;
-    return launch_rc(rb::launch::contract_lp(bf16, pl->nks - pl->nks_s, g, st),
+    return launch_rc(rb::launch::contract_lp(o.precision, pl->nks - pl->nks_s, g, st),
                      "autotune contraction");
   };
   auto timed = [&](auto&& launch, float* ms) -> int {
@@ -995,7 +1003,7 @@ int rb_solve_uneven(rb_ctx* c, int set, int B, const int* Nd, int ldu, const dou
     if (int rc = solve_pack_f64(c, s, g.N, &g.pk)) return rc;
     if (o.precision != RB_PREC_F64) {
       Pack* pl;
-      if (int rc = solve_pack_lp(c, s, g.N, o.precision == RB_PREC_BF16, &pl)) return rc;
+      if (int rc = solve_pack_lp(c, s, g.N, o.precision, &pl)) return rc;
     }
     const auto key = std::make_tuple(set, g.N, o.precision, batch_class(g.Bp));
     if (c->autotune && !c->tune.count(key)) {

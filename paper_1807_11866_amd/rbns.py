@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "librbns.so")
 
 RB_OK, RB_E_INVAL, RB_E_NOMEM, RB_E_DEVICE, RB_E_STATE, RB_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 RB_ST_CONVERGED, RB_ST_MAXIT, RB_ST_SINGULAR, RB_ST_NONFINITE, RB_ST_BADN = 0, 1, 2, 3, 4
-RB_PREC_F64, RB_PREC_F32, RB_PREC_BF16 = 0, 1, 2
+RB_PREC_F64, RB_PREC_F32, RB_PREC_BF16, RB_PREC_BF16X3 = 0, 1, 2, 3
 
 EXPORTED = ("rb_create", "rb_destroy", "rb_last_error", "rb_hbm_used", "rb_load_tensors",
             "rb_theta", "rb_solve_batch", "rb_solve_uneven", "rb_autotune", "rb_tuned_config",

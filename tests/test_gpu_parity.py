@@ -219,8 +219,9 @@ def test_stokes_limit_on_gpu(R, c2):
 
 
 # ------------------------------------------------------------- mixed precision ----
-# Low-precision Newton (FP32 or BF16 tensors on MFMA, FP32 LU, FP64 iterates) followed by
-# refinement steps with the FP64 residual: the result must reach the FP64 oracle within 1e-8.
+# Low-precision Newton (FP32, BF16 or BF16 hi/lo tensors on MFMA, FP32 LU, FP64 iterates)
+# followed by refinement steps with the FP64 residual: the result must reach the FP64 oracle
+# within 1e-8. BF16x3 does so after a single refinement step.
 
 TOL_MIXED = 1e-8
 
@@ -232,7 +233,7 @@ def _mixed(R, s, th, prec, refine, tol=1e-12, max_iter=10):
     return {k: v.cpu().numpy() for k, v in out.items()}
 
 
-@pytest.mark.parametrize("prec,refine", [("F32", 1), ("BF16", 3)])
+@pytest.mark.parametrize("prec,refine", [("F32", 1), ("BF16", 3), ("BF16X3", 1)])
 def test_mixed_precision_parity_ragged(O, R, c2, prec, refine):
     mu = draw_mu(get_config("batched_n50"), 300, seed_offset=11)
     s = R.Solver(c2)
@@ -264,7 +265,7 @@ def test_mixed_converges_to_fp64_tolerance(O, R, c2):
     s = R.Solver(c2)
     th = s.theta(_dev(mu))
     r = O.solve_batch(O.OracleSet(c2), mu)
-    for prec in ("F32", "BF16"):
+    for prec in ("F32", "BF16", "BF16X3"):
         g = _mixed(R, s, th, prec, 12)
         assert np.all(g["status"] == 0), prec
         assert np.max(_rel(g["u"], r["u"])) <= 1e-12, prec
@@ -278,7 +279,7 @@ def test_mixed_random_tensors(O, R, N):
     s = R.Solver(ts)
     th = s.theta(_dev(mu))
     r = O.solve_batch(O.OracleSet(ts), mu, maxit=20)
-    for prec, refine in (("F32", 2), ("BF16", 6)):
+    for prec, refine in (("F32", 2), ("BF16", 6), ("BF16X3", 2)):
         g = _mixed(R, s, th, prec, refine, max_iter=20)
         assert np.all(g["status"] <= 1), prec
         assert np.max(_rel(g["u"], r["u"])) <= TOL_MIXED, prec
@@ -292,7 +293,7 @@ def test_mixed_status_codes(R, c1):
     th["ta"][1].zero_()
     th["tc"][1].zero_()
     th["ta"][2, 0] = float("nan")
-    for prec in ("F32", "BF16"):
+    for prec in ("F32", "BF16", "BF16X3"):
         g = _mixed(R, s, th, prec, 2)
         assert list(g["status"][1:]) == [2, 3], prec
         assert list(g["iters"][1:]) == [0, 0], prec
@@ -325,7 +326,7 @@ def test_mixed_large_n_random(O, R, N):
     s = R.Solver(ts)
     th = s.theta(_dev(mu))
     r = O.solve_batch(O.OracleSet(ts), mu, maxit=20)
-    for prec, refine in (("F32", 2), ("BF16", 6)):
+    for prec, refine in (("F32", 2), ("BF16", 6), ("BF16X3", 2)):
         g = _mixed(R, s, th, prec, refine, max_iter=20)
         assert np.all(g["status"] <= 1), prec
         assert np.max(_rel(g["u"], r["u"])) <= TOL_MIXED, prec
@@ -333,6 +334,7 @@ def test_mixed_large_n_random(O, R, N):
 
 
 @pytest.mark.parametrize("cfg_name,prec,refine", [("mixed_n100", "BF16", 3),
+                                                  ("mixed_n100", "BF16X3", 1),
                                                   ("serve_n150", "F32", 1)])
 def test_mixed_large_configs_sampled(O, R, cfg_name, prec, refine):
     """The synthetic N = 100 / N = 150 sets: ragged batch of 70 requests against the oracle,

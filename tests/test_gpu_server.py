@@ -89,10 +89,12 @@ def test_server_fp64_alone_equals_in_mix(oracle_lib, R):
     _alone_and_in_mix(R, oracle_lib, ts, cfg, R.RB_PREC_F64, 0, 1e-10, pressure=True)
 
 
-def test_server_bf16_serving_set(oracle_lib, R):
+@pytest.mark.parametrize("prec,refine", [("BF16", 4), ("BF16X3", 1)])
+def test_server_bf16_serving_set(oracle_lib, R, prec, refine):
     cfg = get_config("serve_n150")
     ts = make_tensor_set(cfg)
-    _alone_and_in_mix(R, oracle_lib, ts, cfg, R.RB_PREC_BF16, 4, 1e-8, pressure=False)
+    _alone_and_in_mix(R, oracle_lib, ts, cfg, getattr(R, "RB_PREC_" + prec), refine, 1e-8,
+                      pressure=False)
 
 
 def test_server_budget_cuts_batches(R):
