@@ -146,17 +146,30 @@ __device__ __forceinline__ int lu_solve_rows(T (&a)[NP], T rhs, int lane, T* pro
   int pos = lane;
   bool singular = false;
   T mypiv = T(1);
-#pragma unroll
-  for (int k = 0; k < NP; ++k) {
+  // Pivot search of column k over the rows at positions >= k: the wavefront maximum of the
+  // key, the first lane holding it (`tied`: every lane holding it), and, assuming that lane
+  // is the pivot, the pivot value and this row's multiplier. Branch-free, so that the search
+  // of column k+1 is scheduled among the trailing updates of step k.
+  uint64_t tied;
+  int pv;
+  T piv, l;
+  auto search = [&](int k) {
     const bool cand = pos >= k && lane < NP;
     const T av = absv(a[k]);
     uint32_t key = cand ? pivot_key(av) : 0u;
     if (cand && !(av == av)) key = 0xffffffffu;    // a NaN pivot surfaces
     if (cand && key == 0u) key = 1u;               // zero candidates still beat non-candidates
     const uint32_t kmax = wave_max_u32(key);
-    const uint64_t tied = __ballot(key == kmax);
-    int pv = __ffsll(static_cast<unsigned long long>(tied)) - 1;
+    tied = __ballot(key == kmax);
+    pv = __ffsll(static_cast<unsigned long long>(tied)) - 1;
+    piv = bcast(a[k], pv);
+    l = lane == pv ? T(0) : a[k] / (piv == T(0) ? T(1) : piv);
+  };
+  search(0);
+#pragma unroll
+  for (int k = 0; k < NP; ++k) {
     if (__popcll(tied) > 1) {        // same key: exact magnitude, then smallest position
+      const T av = absv(a[k]);
       T bv = bcast(av, pv);
       int best = bcast(pos, pv);
       for (uint64_t m = tied & (tied - 1); m; m &= m - 1) {
@@ -165,16 +178,17 @@ __device__ __forceinline__ int lu_solve_rows(T (&a)[NP], T rhs, int lane, T* pro
         const int p2 = bcast(pos, l2);
         if (v2 > bv || (v2 == bv && p2 < best)) { bv = v2; best = p2; pv = l2; }
       }
+      piv = bcast(a[k], pv);
+      l = lane == pv ? T(0) : a[k] / (piv == T(0) ? T(1) : piv);
     }
-    T piv = bcast(a[k], pv);
     singular |= (piv == T(0));
-    piv = (piv == T(0)) ? T(1) : piv;
-    const int ppos = bcast(pos, pv);
-    const bool me = lane == pv;
+    const int pk = pv;
+    const T lk = l;
+    const int ppos = bcast(pos, pk);
+    const bool me = lane == pk;
     pos = (pos == k) ? ppos : pos;
     pos = me ? k : pos;
-    mypiv = me ? piv : mypiv;
-    const T l = me ? T(0) : a[k] / piv;
+    mypiv = me ? (piv == T(0) ? T(1) : piv) : mypiv;
     if (kLdsBcast) {
       if (me) {
 #pragma unroll
@@ -182,31 +196,35 @@ __device__ __forceinline__ int lu_solve_rows(T (&a)[NP], T rhs, int lane, T* pro
         prow[NP] = rhs;
       }
       wave_lds_order();
-#pragma unroll
-      for (int j0 = k + 1; j0 < NP; j0 += 8) {
+    }
+    // Update of columns j > k in chunks of 8; the pivot row's entries come from `prow` or,
+    // lane -> SGPR (readlane), as the FMA's scalar operand. The search of column k+1 follows
+    // the first chunk (which finishes column k+1) and overlaps the next two.
+    auto chunk = [&](int j0) {
+      if (kLdsBcast) {
         T pj[8];
 #pragma unroll
         for (int t = 0; t < 8; ++t)
           if (j0 + t < NP) pj[t] = prow[j0 + t];
 #pragma unroll
         for (int t = 0; t < 8; ++t)
-          if (j0 + t < NP) a[j0 + t] = fma(-l, pj[t], a[j0 + t]);
-        __builtin_amdgcn_sched_barrier(0);
-      }
-      rhs = fma(-l, prow[NP], rhs);
-      wave_lds_order();
-    } else {
-      // Pivot-row entries go lane -> SGPR (readlane) and feed the FMA as its scalar operand,
-      // in chunks of 8 so the scalar registers in flight stay bounded.
-#pragma unroll
-      for (int j0 = k + 1; j0 < NP; j0 += 8) {
+          if (j0 + t < NP) a[j0 + t] = fma(-lk, pj[t], a[j0 + t]);
+      } else {
 #pragma unroll
         for (int t = 0; t < 8; ++t)
-          if (j0 + t < NP) a[j0 + t] = fma(-l, bcast(a[j0 + t], pv), a[j0 + t]);
-        __builtin_amdgcn_sched_barrier(0);
+          if (j0 + t < NP) a[j0 + t] = fma(-lk, bcast(a[j0 + t], pk), a[j0 + t]);
       }
-      rhs = fma(-l, bcast(rhs, pv), rhs);
+    };
+    chunk(k + 1);
+    __builtin_amdgcn_sched_barrier(0);
+    if (k + 1 < NP) search(k + 1);
+#pragma unroll
+    for (int j0 = k + 9; j0 < NP; j0 += 8) {
+      chunk(j0);
+      if (j0 >= k + 17) __builtin_amdgcn_sched_barrier(0);
     }
+    rhs = fma(-lk, kLdsBcast ? prow[NP] : bcast(rhs, pk), rhs);
+    if (kLdsBcast) wave_lds_order();
   }
   if (lane < NP) prow[pos] = rhs / mypiv;
   wave_lds_order();

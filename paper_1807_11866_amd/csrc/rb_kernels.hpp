@@ -383,10 +383,11 @@ void contract_f64_kernel(ContractArgs a) {
 // One wavefront per request: residual F(u) = (J u + A u)/2 - f, pivoted LU solve of
 // J delta = -F(u), update, and the stopping test ||delta||_H <= tol ||u||_H.
 template <int NP, bool kLdsBcast>
-__global__ __launch_bounds__(kThreads) void lu_f64_kernel(NewtonF64Args a, int it) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(!kLdsBcast && NP <= 56 ? 4 : 1)))
+void lu_f64_kernel(NewtonF64Args a, int it) {
   __shared__ double prow[kWaves][NP + 8];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int b = blockIdx.x * kWaves + wv;
+  const int b = __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves + wv);   // wave-uniform
   if (b >= a.B || a.s.done[b]) return;
   const int N = a.N;
   const int nb = a.nreq ? a.nreq[b] : N;   // this request's size; rows/columns beyond: identity
@@ -396,15 +397,27 @@ __global__ __launch_bounds__(kThreads) void lu_f64_kernel(NewtonF64Args a, int i
   const int lc = lane < N ? lane : N - 1;
   double ju = 0.0;
   bool bad = false;
+  // J row of this lane (sum of the chunk slices), padded to identity beyond the request's
+  // size; loads clamped in bounds.
 #pragma unroll
-  for (int c = 0; c < NP; ++c) r[c] = jb[(c < N ? c : N - 1) * N + lc];   // clamped: in bounds
-  for (int sl = 1; sl < a.s.jslices; ++sl) {               // further chunk slices of J
+  for (int c0 = 0; c0 < NP; c0 += 8) {
+    double v[8];
 #pragma unroll
-    for (int c = 0; c < NP; ++c) r[c] += jb[sl * a.s.jstride + (c < N ? c : N - 1) * N + lc];
+    for (int t = 0; t < 8; ++t)
+      if (c0 + t < NP) v[t] = jb[(c0 + t < N ? c0 + t : N - 1) * N + lc];
+    for (int sl = 1; sl < a.s.jslices; ++sl) {
+#pragma unroll
+      for (int t = 0; t < 8; ++t)
+        if (c0 + t < NP) v[t] += jb[sl * a.s.jstride + (c0 + t < N ? c0 + t : N - 1) * N + lc];
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int c = c0 + t;
+      if (c < NP) r[c] = (c < nb && lane < nb) ? v[t] : (c == lane ? 1.0 : 0.0);
+    }
   }
 #pragma unroll
   for (int c = 0; c < NP; ++c) {
-    r[c] = (c < nb && lane < nb) ? r[c] : (c == lane ? 1.0 : 0.0);
     ju = fma(r[c], ub[c], ju);
     bad |= !finite_val(r[c]);
   }
@@ -587,7 +600,7 @@ template <int NPP, bool kLdsBcast>
 __global__ __launch_bounds__(kThreads) void plu_f64_kernel(PressureF64Args a) {
   __shared__ double prow[kWaves][NPP + 8];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int b = blockIdx.x * kWaves + wv;
+  const int b = __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves + wv);   // wave-uniform
   if (b >= a.B) return;
   const int Np = a.Np;
   const int lc = lane < Np ? lane : Np - 1;

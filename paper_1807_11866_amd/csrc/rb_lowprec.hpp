@@ -326,7 +326,7 @@ template <int NP, bool kRefine>
 __global__ __launch_bounds__(kThreads) void lu_lp_kernel(LpNewtonArgs a, int it) {
   __shared__ float prow[kWaves][NP + 8];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int b = blockIdx.x * kWaves + wv;
+  const int b = __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves + wv);   // wave-uniform
   if (b >= a.B || a.s.done[b]) return;
   const int N = a.N;
   const int nb = a.nreq ? a.nreq[b] : N;   // this request's size; rows/columns beyond: identity
