@@ -293,6 +293,8 @@ def main():
     ap.add_argument("--serve-rates", default="200000,1000000",
                     help="Poisson arrival rates (req/s) of the serving leg ('' = skip)")
     ap.add_argument("--serve-seconds", type=float, default=1.5)
+    ap.add_argument("--autotune", action="store_true",
+                    help="run the library's autotuner on the batch before the warm-up")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the bench, one plain device copy of this many MiB (the "
                          "reference kernel for scaling HBM byte counters)")
@@ -335,6 +337,11 @@ def main():
         s.solve(th, out=out, tol=cfg["tol"], max_iter=cfg["max_iter"], stream=stream)
         s.pressure(th, out["u"], out=pout, stream=stream)
 
+    if args.autotune:
+        rbns.rb_theta(s.ctx, s.set, B, mu, th["ta"], th["tc"], th["tf"], th["tb"], stream)
+        tuned = s.autotune(th, tol=cfg["tol"], max_iter=cfg["max_iter"], stream=stream)
+        torch.cuda.synchronize()
+        log(f"[bench] autotuned (row splits, LDS pivot broadcast) = {tuned}")
     log(f"[bench] warmup {args.warmup} steps (B={B}, N={N})")
     for _ in range(args.warmup):
         step()
