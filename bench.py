@@ -81,7 +81,8 @@ def other_workload(args):
       mixed_n100      B = 32768 at N = 100: BF16 hi/lo tensors (--mixed-prec), FP32 LU, one
                       FP64-residual refinement step
       uneven_n20_100  B = 16384 with N in {20,...,100} in one call (FP32 + refinement)
-      serve_n150      the server under Poisson arrivals, N ~ U{20..150}, FP32 + refinement
+      serve_n150      the server under Poisson arrivals, N ~ U{20..150}, FP32 + two refinement
+                      steps, one lane (--serve-prec, --serve-lanes)
     """
     import torch
     from paper_1807_11866_amd import rbns
@@ -202,11 +203,18 @@ def other_workload(args):
                     traffic=None, kernels=kern)
         roof["frac"] = roof["achieved"] / roof["peak"] if roof["achieved"] else None
     elif name == "serve_n150":
-        metric = "served reduced NS solves/sec, N ~ U{20..150}, Poisson arrivals (FP32 + refinement)"
-        dtype = "f32"
-        rates = [float(x) for x in (args.serve_rates or "20000,50000,100000,200000").split(",")]
-        srv = rbns.Server(s, precision=rbns.RB_PREC_F32, refine_steps=2,
-                          max_iter=cfg["max_iter"], tol=cfg["tol"], max_batch=4096, lanes=3)
+        sp = {"f32": (rbns.RB_PREC_F32, 2), "bf16x3": (rbns.RB_PREC_BF16X3, 1),
+              "bf16": (rbns.RB_PREC_BF16, 4)}
+        prec, refine = sp[args.serve_prec]
+        metric = (f"served reduced NS solves/sec, N ~ U{{20..150}}, Poisson arrivals "
+                  f"({args.serve_prec.upper()} + {refine} FP64-residual refinement step(s))")
+        dtype = args.serve_prec
+        rates = [float(x) for x in (args.serve_rates or "20000,50000,100000,200000").split(",")
+                 if x.strip()]
+        srv = rbns.Server(s, precision=prec, refine_steps=refine, max_iter=cfg["max_iter"],
+                          tol=cfg["tol"], max_batch=4096, lanes=args.serve_lanes)
+        extra["refine_steps"] = refine
+        extra["lanes"] = args.serve_lanes
         served = {}
         Bp = 8192
         mu_s = draw_mu(cfg, Bp)
@@ -290,9 +298,14 @@ def main():
                          "1 for bf16x3, 3 for bf16)")
     ap.add_argument("--mixed-prec", choices=("bf16x3", "bf16"), default="bf16x3",
                     help="tensor format of the mixed-precision leg / workload")
-    ap.add_argument("--serve-rates", default="200000,1000000",
-                    help="Poisson arrival rates (req/s) of the serving leg ('' = skip)")
+    ap.add_argument("--serve-rates", default=None,
+                    help="Poisson arrival rates (req/s) of the serving leg ('' = skip; default "
+                         "200000,1000000, and 20000,50000,100000,200000 for serve_n150)")
     ap.add_argument("--serve-seconds", type=float, default=1.5)
+    ap.add_argument("--serve-prec", choices=("f32", "bf16x3", "bf16"), default="f32",
+                    help="tensor format of the serve_n150 workload")
+    ap.add_argument("--serve-lanes", type=int, default=1,
+                    help="server lanes (batches in flight) of the serve_n150 workload")
     ap.add_argument("--autotune", action="store_true",
                     help="run the library's autotuner on the batch before the warm-up")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -475,7 +488,8 @@ def main():
             f"{mix['value']:.4g} solves/s")
 
     # ---- served: continuous batching under Poisson arrivals --------------------------------
-    rates = [float(r) for r in args.serve_rates.split(",") if r.strip()]
+    srates = "200000,1000000" if args.serve_rates is None else args.serve_rates
+    rates = [float(r) for r in srates.split(",") if r.strip()]
     if rates:
         served = {}
         srv = rbns.Server(s, precision=rbns.RB_PREC_F64, max_iter=cfg["max_iter"],

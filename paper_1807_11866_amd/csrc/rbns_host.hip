@@ -8,6 +8,7 @@
 #include <cstring>
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <deque>
 #include <map>
@@ -1394,10 +1395,17 @@ int launch_batch(rb_server* v, Lane& L) {
   int* stt = it + v->cap;
   int* pst = it + 2 * v->cap;
   rb_solve_opts o = {v->o.tol, v->o.max_iter, v->o.precision, v->o.refine_steps};
+  // Groups (largest N first) go to the sub-stream with the least work queued so far
+  // (longest-processing-time-first); a group's time grows about as N^1.5 and, at these small
+  // batch sizes, only weakly with its request count.
+  double load[kSubStreams] = {};
   int r0 = 0;
   for (size_t gi = 0; gi < groups.size(); ++gi) {
     const auto& g = groups[gi];
-    hipStream_t gst = L.sub[gi % kSubStreams];
+    int k = 0;
+    for (int q = 1; q < nsub; ++q) k = load[q] < load[k] ? q : k;
+    load[k] += std::pow((double)g.first, 1.5) * std::sqrt((double)((g.second + 63) / 64));
+    hipStream_t gst = L.sub[k];
     const int N = g.first, n = g.second;
     const int64_t Bp = ceil_to(n, rb::kTile);
     Pack* pk;
