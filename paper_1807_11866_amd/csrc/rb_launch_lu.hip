@@ -1,5 +1,6 @@
-// Instantiations of the FP64 LU kernels (Newton step and pressure solve) per size bucket
-// NP in 4..64 (multiples of 4), and the dispatcher over the mode-specific contraction TUs.
+// Instantiations of the FP64 LU kernels per size bucket: Newton step NP in 2..64 (even),
+// pressure solve NPP in 4..64 (multiples of 4); and the dispatcher over the mode-specific
+// contraction TUs.
 #include "rb_launch.hpp"
 
 namespace rb {
@@ -33,12 +34,15 @@ static int go_plu(const PressureF64Args& a, bool lds, hipStream_t st) {
 
 #define RB_NP_CASES(X) X(4) X(8) X(12) X(16) X(20) X(24) X(28) X(32) X(36) X(40) X(44) X(48) \
   X(52) X(56) X(60) X(64)
+#define RB_NP_ODD2(X) X(2) X(6) X(10) X(14) X(18) X(22) X(26) X(30) X(34) X(38) X(42) X(46) \
+  X(50) X(54) X(58) X(62)
 
 int lu_f64(int NP, const NewtonF64Args& a, int it, bool lds, hipStream_t st) {
   if (NP > 64) return lu_f64_mw(NP, a, it, st);
   switch (NP) {
 #define RB_C(n) case n: return go_lu<n>(a, it, lds, st);
     RB_NP_CASES(RB_C)
+    RB_NP_ODD2(RB_C)
 #undef RB_C
   }
   return -5;
