@@ -1,6 +1,5 @@
-// Instantiations of the FP64 LU kernels per size bucket: Newton step NP in 2..64 (even),
-// pressure solve NPP in 4..64 (multiples of 4); and the dispatcher over the mode-specific
-// contraction TUs.
+// Instantiations of the FP64 LU kernels (Newton step and pressure solve) per size bucket
+// NP in 2..64 (even), and the dispatcher over the mode-specific contraction TUs.
 #include "rb_launch.hpp"
 
 namespace rb {
@@ -52,6 +51,7 @@ int plu_f64(int NPP, const PressureF64Args& a, bool lds, hipStream_t st) {
   switch (NPP) {
 #define RB_C(n) case n: return go_plu<n>(a, lds, st);
     RB_NP_CASES(RB_C)
+    RB_NP_ODD2(RB_C)
 #undef RB_C
   }
   return -5;

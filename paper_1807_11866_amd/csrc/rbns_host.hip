@@ -331,19 +331,15 @@ int jslices_for(const Set* s, int N, int precision) {
   return n;
 }
 
-// Register row length of the pressure LU: multiples of 4 up to 64 (one wavefront per system),
-// multiples of 8 beyond.
-int np_bucket(int n) { return (int)ceil_to(n, n <= 64 ? 4 : 8); }
-
-// Register row length of the Newton LU kernels: even up to 64 (one wavefront per system;
-// every padded column costs a pivot step and a column of updates), multiples of 8 beyond
-// (one workgroup of ceil(NP/64) wavefronts per system).
-int np_solve(int n) { return (int)ceil_to(n, n <= 64 ? 2 : 8); }
+// Register row length of the LU kernels (Newton and pressure): even up to 64 (one wavefront
+// per system; every padded column costs a pivot step and a column of updates), multiples of
+// 8 beyond (one workgroup of ceil(NP/64) wavefronts per system).
+int np_bucket(int n) { return (int)ceil_to(n, n <= 64 ? 2 : 8); }
 
 // Workspace of one same-N batch (padded to Bp requests): Newton state plus, for the mixed
 // precisions, the low-precision buffers.
 size_t solve_bytes(const Set* s, int N, int64_t Bp, int nsplit, int precision) {
-  const int NP = np_solve(N);
+  const int NP = np_bucket(N);
   const int64_t mp = ceil_to((int64_t)N * N, 16);
   size_t b = newton_state_bytes(Bp, NP, mp, nsplit, jslices_for(s, N, precision));
   if (precision != RB_PREC_F64) b += lp_extra_bytes(Bp, NP, mp, nsplit);
@@ -585,7 +581,7 @@ rb::NewtonF64Args make_args(Set* s, Pack* pk, int N, int B, int ldu, const rb_so
   a.H = s->hasH ? (const double*)s->H.p : nullptr;
   a.u = u; a.iters = iters; a.status = status;
   const int64_t Bp = ceil_to(B, rb::kTile);
-  a.s = carve_state(region, Bp, np_solve(N), ceil_to((int64_t)N * N, 16), nsplit,
+  a.s = carve_state(region, Bp, np_bucket(N), ceil_to((int64_t)N * N, 16), nsplit,
                     jslices_for(s, N, o.precision));
   return a;
 }
