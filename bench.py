@@ -404,6 +404,7 @@ def main():
         kern[f]["kernel"], kern[f]["bound"], kern[f]["peak_tflops"] = names[f]
         a = kern[f]["achieved_tflops"]
         kern[f]["frac"] = a / names[f][2] if a else None
+        kern[f]["traffic"] = recorded_traffic(f)        # HBM bytes per launch (profiled)
     dominant = max(fams, key=lambda f: fams[f][0])
     d = kern[dominant]
     roof = dict(bound=d["bound"], achieved=d["achieved_tflops"], peak=d["peak_tflops"],
