@@ -261,11 +261,10 @@ typedef struct {
     int max_iter;             /* Newton iteration limit                                     */
     double tol;               /* Newton tolerance                                           */
     int max_batch;            /* requests per batch (1..65536)                              */
-    int lanes;                /* batches in flight at once (1..4). Each lane uses 5 streams
-                                 (its own + 4 for the size-class groups of its batch); with the
-                                 process's 4 hardware queues, 1 lane gives the lowest latency
-                                 for batches of many size classes, several lanes help a single
-                                 class whose batches are short                               */
+    int lanes;                /* batches in flight at once (1..4). Each lane uses 7 streams
+                                 (its own + 6 for the size-class groups of its batch); 1 lane
+                                 gives the lowest latency for batches of many size classes,
+                                 several lanes help a single class whose batches are short   */
     size_t hbm_budget_bytes;  /* workspace of the batches in flight (0: no limit): a batch is
                                  cut (halved until it fits) beside the batches in flight, or
                                  waits for them to finish; alone it runs at any size        */
