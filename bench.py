@@ -196,6 +196,10 @@ def other_workload(args):
         if fams["residual"][0] > 0:
             kern["residual"].update(achieved_tflops=res_flops / (fams["residual"][0] * 1e-3) / 1e12,
                                     peak_tflops=78.6, bound="mfma")
+        if fams["lu"][0] > 0:       # FP32 LU (both phases): 2N^3/3 + 4N^2 per Newton update
+            lu_flops = float(((2.0 / 3.0 * Nreq ** 3 + 4.0 * Nreq ** 2) * its).sum()) * nsteps
+            kern["lu"].update(achieved_tflops=lu_flops / (fams["lu"][0] * 1e-3) / 1e12,
+                              peak_tflops=157.3, bound="alu")
         dominant = max(fams, key=lambda f: fams[f][0])
         d = kern[dominant]
         roof = dict(bound=d.get("bound", "alu"), achieved=d.get("achieved_tflops"),
