@@ -120,9 +120,9 @@ __host__ __device__ inline int64_t contract_lp_lds_bytes(int N) {
 // one chunk. kS3 (BF16x3): operand and W are both split into hi + lo BF16 parts and every
 // product is hi*hi + hi*lo + lo*hi (three MFMAs, about 16 mantissa bits). Accumulator layout
 // of the 16x16 FP32 MFMAs: lane l, element v = row 4*(l/16) + v, column l%16.
-template <bool kBF16, int KT, bool kS3 = false>
-// BF16x3 with KT <= 14: two waves per SIMD (hi + lo W in registers leave room for a
+// BF16x3 with KT <= 14 runs two waves per SIMD (hi + lo W in registers leave room for a
 // two-k-step prefetch only); measured 26 % faster than one wave with a six-step prefetch.
+template <bool kBF16, int KT, bool kS3 = false>
 __global__ __launch_bounds__(kThreads)
 __attribute__((amdgpu_waves_per_eu(kS3 && KT <= 14 ? 2 : 1)))
 void contract_lp_kernel(ContractLpArgs a) {
