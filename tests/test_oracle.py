@@ -309,3 +309,72 @@ def test_block_triangular_equals_coupled_solve(O, c2):
     assert st == 0 and sp == 0
     assert np.linalg.norm(res_v) <= 1e-10 * np.linalg.norm(tf @ c2.F)
     assert np.linalg.norm(res_s) <= 1e-12 * np.linalg.norm(tf @ c2.Fs)
+
+
+def _leray_case():
+    """Qc = 1 synthetic set (N = Np = 8, |k| <= 6, 32 x 32 grid), a random velocity u in the
+    span, and the pressure the continuous equations give for it.
+
+    With M_0 = I the convection form is the true one, and at alpha = 0 the pressure form is
+    b_0(p, w) = -int p div w. The supremizers solve -Laplace(s_i) = grad(p_i), so
+    div(s_i) = -p_i and b_0(p_j, s_i) = (p_j, p_i) = delta_ij. They are gradients, so every
+    solenoidal field is L2-orthogonal to them and A_sv = 0. The recovery equation
+    b(p, s_i) = (g, s_i) - c(u, u, s_i) therefore reads (p, p_i) = (w, s_i) with
+    w = g - (u . grad) u; writing w = w_sol + grad(P) (Leray), (w, s_i) = (grad P, s_i) =
+    (P, p_i). So the recovered coefficients are the L2 projections (P, p_i) of the Leray
+    pressure P, which solves Laplace(P) = div(w). P is computed here by FFT on the grid, a
+    route that shares nothing with the tensors' quadrature.
+    """
+    from rbinputs import synth as S
+    seeds = get_config("single_n10")["seeds"]
+    N, Np, kmax, G = 8, 8, 6, 32
+    d = S.assemble(N, Np, kmax, G, 3, 1, 1, 2, seeds, forcing_scale=1.0)
+    K = d["K"]
+    E = S.grid_modes(K, G)
+    u = np.random.default_rng(11).standard_normal(N)
+    Uc = np.tensordot(u, d["phi_c"], 1)                                  # (2, W, 2)
+    U = S.on_grid(Uc, E)                                                 # (2, G^2)
+    dU = np.stack([S.on_grid(S.deriv(Uc, K, a), E) for a in range(2)])   # dU[a, b] = d_a U^b
+    w = S.on_grid(d["g_c"][0], E) - np.einsum("ax,abx->bx", U, dU)
+    wh = [np.fft.fft2(w[b].reshape(G, G)) for b in range(2)]
+    f = np.fft.fftfreq(G, d=1.0 / G)
+    KX, KY = np.meshgrid(f, f, indexing="ij")                            # grid is x-major
+    k2 = KX ** 2 + KY ** 2
+    k2[0, 0] = 1.0
+    Ph = -1j * (KX * wh[0] + KY * wh[1]) / (2.0 * np.pi * k2)           # Laplace P = div w
+    Ph[0, 0] = 0.0
+    P = np.fft.ifft2(Ph).real.reshape(-1)
+    p_expected = S.on_grid(d["p_c"], E) @ P / G ** 2                     # (P, p_i)
+    return d, u, p_expected
+
+
+def _leray_set(d, **over):
+    kw = dict(A=d["A"], C=d["C"], F=d["F"], H=d["H"], Bp=d["Bp"], Asv=d["Asv"], Csv=d["Csv"],
+              Fs=d["Fs"])
+    kw.update(over)
+    return TensorSet(N=8, Q=3, Qc=1, Qf=1, Np=8, Qb=2, **kw)
+
+
+def test_pressure_velocity_terms_leray_projection(O):
+    """The velocity-dependent part of the recovery (C_sv(u, u), with A_sv(u) = 0), pinned by
+    the continuous pressure of eqn sup-vvar: the recovered p is the L2 projection of the
+    Leray pressure of g - (u . grad) u onto the pressure basis."""
+    d, u, p_exp = _leray_case()
+    ta, tc, tf, tb = O.theta(3, 1, 1, 2, 0.0, 300.0)
+    p, st = O.pressure(O.OracleSet(_leray_set(d)), 8, 8, ta, tc, tf, tb, u)
+    assert st == 0
+    assert np.linalg.norm(p_exp) > 0.1                      # the velocity term matters
+    assert np.max(np.abs(p - p_exp)) <= 1e-12 * np.max(np.abs(p_exp))
+
+
+@pytest.mark.parametrize("plant", ["flipped_sign", "test_index_slot", "dropped_term"])
+def test_pressure_leray_catches_planted_mistakes(O, plant):
+    """A flipped sign of the convection term, the test index in the advecting slot, or a
+    dropped convection term each move the recovered pressure by O(1) against the pin."""
+    d, u, p_exp = _leray_case()
+    Csv = {"flipped_sign": -d["Csv"],
+           "test_index_slot": np.ascontiguousarray(d["Csv"].transpose(0, 2, 1, 3)),
+           "dropped_term": np.zeros_like(d["Csv"])}[plant]
+    ta, tc, tf, tb = O.theta(3, 1, 1, 2, 0.0, 300.0)
+    p, _ = O.pressure(O.OracleSet(_leray_set(d, Csv=Csv)), 8, 8, ta, tc, tf, tb, u)
+    assert np.max(np.abs(p - p_exp)) > 0.1 * np.max(np.abs(p_exp))
