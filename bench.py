@@ -74,6 +74,57 @@ def rel_err(a, b):
     return np.linalg.norm(a - b, axis=-1) / np.where(nb > 0, nb, 1.0)
 
 
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo, as lscpu reports it)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(ts, mu_h, cfg, args):
+    """The oracle (velocity Newton + pressure recovery, FP64) on the host cores: first on all
+    threads (OpenMP over requests, chunks of 512 requests), then on one core one request per
+    call, for the per-solve p50/p99; each for half of --cpu-seconds."""
+    import oracle  # CPU reference (test infrastructure)
+    oset = oracle.OracleSet(ts)
+    B, Np = mu_h.shape[0], ts.Np
+    half = 0.5 * args.cpu_seconds
+    done, tc0, threads = 0, time.perf_counter(), 0
+    while time.perf_counter() - tc0 < half:
+        sel = np.arange(done, done + 512) % B
+        r = oracle.solve_batch(oset, mu_h[sel], pressure_np=Np, tol=cfg["tol"],
+                               maxit=cfg["max_iter"], nthreads=0)
+        threads = r["threads"]
+        done += 512
+    tc1 = time.perf_counter()
+    per = []
+    t1c = time.perf_counter()
+    while time.perf_counter() - t1c < half:
+        i = len(per) % B
+        ta = time.perf_counter()
+        oracle.solve_batch(oset, mu_h[i:i + 1], pressure_np=Np, tol=cfg["tol"],
+                           maxit=cfg["max_iter"], nthreads=1)
+        per.append(time.perf_counter() - ta)
+    per_ms = 1e3 * np.asarray(per)
+    cpu = dict(value=done / (tc1 - tc0), unit="solves/s", cores=int(threads), kind="oracle",
+               cpu_model=cpu_model(),
+               sample=f"{done} requests of the {args.workload} workload on {threads} threads "
+                      f"(velocity Newton + pressure recovery, FP64, OpenMP over requests, "
+                      f"{tc1 - tc0:.1f} s); then {len(per)} requests one per call on 1 core",
+               single_core=dict(value=len(per) / per_ms.sum() * 1e3, unit="solves/s", cores=1,
+                                requests=len(per), p50_ms=float(np.percentile(per_ms, 50)),
+                                p99_ms=float(np.percentile(per_ms, 99))))
+    log(f"[bench] cpu oracle: {cpu['value']:.4g} solves/s on {threads} threads, "
+        f"{cpu['single_core']['value']:.4g} solves/s on 1 core "
+        f"(p50 {cpu['single_core']['p50_ms']:.3f} ms, p99 {cpu['single_core']['p99_ms']:.3f} ms)")
+    return cpu
+
+
 def other_workload(args):
     """The other synthetic workloads, each timed the same way (inputs resident, HIP-event
     kernel timing, oracle check on a sample):
@@ -304,7 +355,8 @@ def main():
                     help="tensor format of the mixed-precision leg / workload")
     ap.add_argument("--serve-rates", default=None,
                     help="Poisson arrival rates (req/s) of the serving leg ('' = skip; default "
-                         "200000,1000000, and 20000,50000,100000,200000 for serve_n150)")
+                         "20000,50000,100000,200000,1000000, and 20000,50000,100000,200000 "
+                         "for serve_n150)")
     ap.add_argument("--serve-seconds", type=float, default=1.5)
     ap.add_argument("--serve-prec", choices=("f32", "bf16x3", "bf16"), default="f32",
                     help="tensor format of the serve_n150 workload")
@@ -493,7 +545,8 @@ def main():
             f"{mix['value']:.4g} solves/s")
 
     # ---- served: continuous batching under Poisson arrivals --------------------------------
-    srates = "200000,1000000" if args.serve_rates is None else args.serve_rates
+    srates = ("20000,50000,100000,200000,1000000" if args.serve_rates is None
+              else args.serve_rates)
     rates = [float(r) for r in srates.split(",") if r.strip()]
     if rates:
         served = {}
@@ -512,6 +565,7 @@ def main():
                 sel = np.arange(n) % B
                 st0 = srv.stats()
                 lat = np.full(n, np.nan)
+                qw = np.full(n, np.nan)
                 stat = np.full(n, -1, dtype=np.int64)
                 chk = [k for k in range(n) if int(sel[k]) in pos][:len(idx)]
                 chk_set = {k: m for m, k in enumerate(chk)}
@@ -530,6 +584,7 @@ def main():
                     if len(ra):
                         tg = ra["tag"]
                         lat[tg] = ra["latency_ms"]
+                        qw[tg] = ra["queue_ms"]
                         stat[tg] = ra["status"]
                         got += len(ra)
                         for r in ra:
@@ -544,6 +599,8 @@ def main():
                 ent = dict(offered_req_s=rate, requests=n, value=n / (t1s - t0s),
                            unit="solves/s", p50_ms=float(np.percentile(lat, 50)),
                            p99_ms=float(np.percentile(lat, 99)), max_ms=float(lat.max()),
+                           p50_queue_ms=float(np.percentile(qw, 50)),
+                           p99_queue_ms=float(np.percentile(qw, 99)),
                            batches=int(st1["batches"] - st0["batches"]),
                            status_hist=np.bincount(stat, minlength=6).tolist())
                 ent["mean_batch"] = n / max(ent["batches"], 1)
@@ -561,22 +618,7 @@ def main():
     # ---- CPU baseline: the oracle as it stands, bounded sample of the same workload --------
     cpu = None
     if not args.no_cpu:
-        import oracle  # CPU reference (test infrastructure)
-        oset = oracle.OracleSet(ts)
-        done, tc0 = 0, time.perf_counter()
-        threads = 0
-        chunk = 512
-        while time.perf_counter() - tc0 < args.cpu_seconds:
-            sel = np.arange(done, done + chunk) % B
-            r = oracle.solve_batch(oset, mu_h[sel], pressure_np=Np, tol=cfg["tol"],
-                                   maxit=cfg["max_iter"], nthreads=0)
-            threads = r["threads"]
-            done += chunk
-        tc1 = time.perf_counter()
-        cpu = dict(value=done / (tc1 - tc0), unit="solves/s", cores=int(threads), kind="oracle",
-                   sample=f"{done} requests of the {args.workload} workload (velocity Newton + "
-                          f"pressure recovery, FP64, OpenMP over requests), {tc1 - tc0:.1f} s")
-        log(f"[bench] cpu oracle: {cpu['value']:.4g} solves/s on {threads} threads")
+        cpu = cpu_baseline(ts, mu_h, cfg, args)
 
     res = {
         "metric": "reduced NS solves/sec at N=50 (batched, velocity Newton + pressure recovery)",

@@ -246,7 +246,8 @@ int rb_recover_pressure(rb_ctx *ctx, int set, int B, int N, int Np, int ldu, int
  * of that size (theta(mu) on the device, Newton, optionally the pressure), every request as
  * the leading N x N block of the group's system with its other unknowns held at zero; the
  * tile shapes depend on the group only, so a request's result does not depend on the other
- * requests of its batch. rb_server_poll hands back finished
+ * requests of its batch (a group's row splits are fixed by its N alone, never by the batch size or
+ * the tuning table). rb_server_poll hands back finished
  * results (with the latency from submission to the moment the worker saw the batch finish).
  * The tensor set stays resident; each lane keeps its buffers and workspace between batches.
  * Stop every server of a context before rb_destroy.
@@ -281,13 +282,17 @@ typedef struct {
     long long ticket, tag;
     int N, status, iters, pstatus;
     double latency_ms;        /* submission -> batch completion seen by the worker          */
+    double queue_ms;          /* submission -> launch of its batch (the rest of latency_ms is
+                                 the batch on the GPU plus the copy back)                     */
     double u[RB_MAX_N];       /* velocity coefficients (first N valid, rest 0)              */
     double p[RB_MAX_NP];      /* pressure coefficients (first Np valid) if opts.pressure    */
 } rb_result;
 
 typedef struct {
     long long submitted, completed, batches;
-    double p50_ms, p99_ms, max_ms;   /* latency quantiles over the completed requests      */
+    double p50_ms, p99_ms, max_ms;   /* latency quantiles over the completed requests
+                                        (log-spaced histogram: within 0.5 %; max exact)     */
+    double p50_queue_ms, p99_queue_ms;   /* same for the wait before the batch launch       */
     double mean_batch;               /* requests per batch                                  */
     double first_submit_s, last_done_s;   /* on the server's clock (seconds since start)   */
     size_t hbm_inflight_peak;        /* largest workspace estimate of batches in flight    */

@@ -286,6 +286,7 @@ void contract_f64_kernel(ContractArgs a) {
   auto pass = [&](auto nks_c, const double* w, int k_first, int chunk) {
     constexpr int NKS = decltype(nks_c)::value;
     constexpr bool kAff = NKS == kAmax + KC;   // this pass starts with the affine k-steps
+    if (rb_lo >= rb_hi) return;            // no row blocks in this split: load nothing
     auto row_ptr = [&](int rb) {
       return a.op + (int64_t)min(rb, rb_hi - 1) * a.nks * 64 + (int64_t)k_first * 64 + lane;
     };

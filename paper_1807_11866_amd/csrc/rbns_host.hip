@@ -110,6 +110,8 @@ struct rb_ctx {
   // graph cache and the shapes seen once (captured on their second occurrence)
   int* pin = nullptr;
   size_t pin_cap = 0;
+  hipEvent_t pin_ev = nullptr;          // recorded after the last copy out of `pin`
+  bool pin_busy = false;
   hipStream_t cap_stream = nullptr;
   std::vector<hipStream_t> branches;
   std::vector<GraphEntry> graphs;
@@ -484,17 +486,24 @@ int enqueue_newton_lp(rb_ctx* c, Set* s, const rb::NewtonF64Args& a, int prec, i
 
 int default_nsplit(int64_t Bp, int nrows);
 
-size_t pressure_bytes(int B, int N, int Np) {
+// Row splits of a pressure recovery of B requests: `nsplit`, or 0 for the default of the
+// batch size.
+int pressure_nsplit(int B, int N, int Np, int nsplit) {
+  return nsplit > 0 ? nsplit : default_nsplit(ceil_to(B, rb::kTile), Np * N);
+}
+
+size_t pressure_bytes(int B, int N, int Np, int nsplit = 0) {
   const int64_t Bp = ceil_to(B, rb::kTile);
-  return (size_t)default_nsplit(Bp, Np * N) * Bp * np_bucket(Np) * sizeof(double);
+  return (size_t)pressure_nsplit(B, N, Np, nsplit) * Bp * np_bucket(Np) * sizeof(double);
 }
 
 // Pressure recovery of B requests at (N, Np) (eqn sup-vvar): the pressure-operand
-// contraction (A_sv u + C_sv(u,u), default_nsplit partial sums at `part`, pressure_bytes
-// long) and the pivoted LU solve B(mu) p = f_s - A_sv u - C_sv(u,u).
+// contraction (A_sv u + C_sv(u,u), partial sums of `nsplit` row splits (0: the default) at
+// `part`, pressure_bytes long) and the pivoted LU solve B(mu) p = f_s - A_sv u - C_sv(u,u).
 int enqueue_pressure(rb_ctx* c, Set* s, int B, int N, int Np, int ldu, int ldp,
                      const double* ta, const double* tc, const double* tf, const double* tb,
-                     const double* u, double* p, int* status, char* part, hipStream_t st) {
+                     const double* u, double* p, int* status, char* part, hipStream_t st,
+                     int nsplit = 0) {
   Pack* pk;
   if (int rc = press_pack_f64(c, s, N, Np, &pk)) return rc;
   const int NPP = np_bucket(Np);
@@ -508,7 +517,7 @@ int enqueue_pressure(rb_ctx* c, Set* s, int B, int N, int Np, int ldu, int ldp,
   g.U = u; g.ldU = ldu;
   g.done = nullptr;
   g.J = nullptr; g.mp = 0; g.jstride = 0;
-  g.part = (double*)part; g.ldp = NPP; g.nsplit = default_nsplit(Bp, Np * N);
+  g.part = (double*)part; g.ldp = NPP; g.nsplit = pressure_nsplit(B, N, Np, nsplit);
   rb::PressureF64Args a;
   a.Np = Np; a.Npm = s->Np; a.Qf = s->Qf; a.Qb = s->Qb; a.B = B; a.ldp = ldp; a.Bp = Bp;
   a.tf = tf; a.tb = tb;
@@ -539,7 +548,7 @@ int default_nsplit(int64_t Bp, int nrows) {
   int want = rb::kSplit;
   while (want < rb::kMaxSplit && tiles * want < 512) want *= 2;
   const int nrb = (nrows + 15) / 16;
-  return std::max(1, std::min(want, std::max(rb::kSplit, nrb / 4)));
+  return std::max(1, std::min({want, std::max(rb::kSplit, nrb / 4), nrb}));
 }
 
 // Partial-sum slots a state region reserves so that the autotuner can try every candidate.
@@ -653,7 +662,7 @@ int autotune_batch(rb_ctx* c, Set* s, int set, rb::NewtonF64Args a, const rb_sol
   best.lu_lds = c->lu_lds;
   float best_ms = 1e30f;
   for (int ns : {2, 4, 8, 16, default_nsplit(Bp, N * N)}) {
-    if (ns > rsplit || (ns > 2 && ns > a.nrb)) continue;   // no slots / more splits than rows
+    if (ns > rsplit || ns > a.nrb) continue;   // no slots / more splits than row blocks
     float ms = 0.f;
     if (int rc = timed([&] { return contract(ns); }, &ms)) return release(rc);
     if (ms < best_ms) {
@@ -677,13 +686,27 @@ int autotune_batch(rb_ctx* c, Set* s, int set, rb::NewtonF64Args a, const rb_sol
   return release(RB_OK);
 }
 
+// The pinned staging buffer is shared by every stream of the context: an uneven call's
+// asynchronous copy of the permutation out of it may still be pending on another stream, so
+// wait for that copy before the buffer is rewritten or replaced.
 int ensure_pinned(rb_ctx* c, size_t ints) {
+  if (c->pin_busy) {
+    HIP_TRY(hipEventSynchronize(c->pin_ev));
+    c->pin_busy = false;
+  }
   if (c->pin_cap >= ints) return RB_OK;
   if (c->pin) HIP_TRY(hipHostFree(c->pin));
   c->pin = nullptr;
   c->pin_cap = 0;
   HIP_TRY(hipHostMalloc((void**)&c->pin, ints * sizeof(int), hipHostMallocDefault));
   c->pin_cap = ints;
+  return RB_OK;
+}
+
+int pin_release(rb_ctx* c, hipStream_t st) {
+  if (!c->pin_ev) HIP_TRY(hipEventCreateWithFlags(&c->pin_ev, hipEventDisableTiming));
+  HIP_TRY(hipEventRecord(c->pin_ev, st));
+  c->pin_busy = true;
   return RB_OK;
 }
 
@@ -747,6 +770,10 @@ int rb_destroy(rb_ctx* c) {
   }
   for (auto b : c->branches) (void)hipStreamDestroy(b);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  if (c->pin_ev) {
+    (void)hipEventSynchronize(c->pin_ev);
+    (void)hipEventDestroy(c->pin_ev);
+  }
   if (c->pin) (void)hipHostFree(c->pin);
   delete c;
   return RB_OK;
@@ -914,7 +941,8 @@ int rb_solve_uneven(rb_ctx* c, int set, int B, const int* Nd, int ldu, const dou
   hipStream_t st = (hipStream_t)stream;
   const int Nm = s->N;
 
-  // 1. per-request sizes to the host (drains st, so the pinned buffer is free again)
+  // 1. per-request sizes to the host (ensure_pinned waits for any copy still reading the
+  //    pinned buffer, on whichever stream it was queued)
   if (int rc = ensure_pinned(c, (size_t)3 * B + 64 * 160)) return rc;
   int* hN = c->pin;
   HIP_TRY(hipMemcpyAsync(hN, Nd, (size_t)B * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -989,6 +1017,7 @@ int rb_solve_uneven(rb_ctx* c, int set, int B, const int* Nd, int ldu, const dou
   }
   HIP_TRY(hipMemcpyAsync(base + o_perm, hp, (size_t)(Bs + nbad) * sizeof(int),
                          hipMemcpyHostToDevice, st));
+  if (int rc = pin_release(c, st)) return rc;
   if (Bs > 0)
     hipLaunchKernelGGL(rb::uneven_gather_kernel, dim3(launch_grid(Bs * Nm)), dim3(256), 0, st, io);
   HIP_TRY(hipGetLastError());
@@ -1201,6 +1230,7 @@ int rb_recover_pressure_uneven(rb_ctx* c, int set, int B, const int* Nd, int Np,
   }
   HIP_TRY(hipMemcpyAsync(base + o_perm, hp, (size_t)(Bs + nbad) * sizeof(int),
                          hipMemcpyHostToDevice, st));
+  if (int rc = pin_release(c, st)) return rc;
   // gather theta and u (into the u0 staging slot) in group order
   rb::UnevenIo io{};
   io.Bs = Bs; io.nbad = nbad; io.perm = (const int*)(base + o_perm);
@@ -1286,6 +1316,32 @@ struct Pending {
   Clock::time_point t_submit;
 };
 
+// Latency quantiles in bounded memory: log-spaced bins of ratio 1.01 from 1 us to 1000 s
+// (2083 bins), so a quantile is known to within 0.5 %, whatever the number of requests.
+struct LatHist {
+  static constexpr double kLo = 1e-3, kRatio = 1.01;   // ms
+  std::vector<uint64_t> bins = std::vector<uint64_t>(2084, 0);
+  uint64_t n = 0;
+  double maxv = 0.0;
+  void add(double ms) {
+    const double x = std::max(ms, kLo);
+    const size_t b = std::min(bins.size() - 1, (size_t)(std::log(x / kLo) / std::log(kRatio)));
+    ++bins[b];
+    ++n;
+    maxv = std::max(maxv, ms);
+  }
+  double quantile(double f) const {
+    if (n == 0) return 0.0;
+    const uint64_t want = std::min<uint64_t>(n - 1, (uint64_t)(f * (double)(n - 1) + 0.5));
+    uint64_t seen = 0;
+    for (size_t b = 0; b < bins.size(); ++b) {
+      seen += bins[b];
+      if (seen > want) return std::min(maxv, kLo * std::pow(kRatio, (double)b + 0.5));
+    }
+    return maxv;
+  }
+};
+
 // One lane: a stream, its device buffers for max_batch requests and pinned host mirrors. The
 // size-class groups of a batch run concurrently on the lane's sub-streams (forked from and
 // joined back into the lane stream with events).
@@ -1299,6 +1355,7 @@ struct Lane {
   hipEvent_t fork = nullptr;
   hipEvent_t join[kSubStreams] = {};
   bool busy = false;
+  Clock::time_point t_launch;         // when the batch in flight was launched
   size_t need = 0;                    // workspace estimate of the batch in flight
   std::vector<Pending> batch;         // in the order of the device rows (grouped by N)
   DevBuf d_mu, d_ta, d_tc, d_tf, d_tb, d_u, d_p, d_int, d_n;
@@ -1325,7 +1382,7 @@ struct rb_server {
   std::deque<rb_result> results;
   bool stopping = false;
   long long next_ticket = 1, submitted = 0, completed = 0, batches = 0;
-  std::vector<double> lat_ms;
+  LatHist lat, wait;                  // latency and queue-wait histograms
   Clock::time_point t0;
   double first_submit_s = -1.0, last_done_s = 0.0;
   size_t inflight = 0, inflight_peak = 0;
@@ -1341,16 +1398,29 @@ namespace {
 // depend on the rest of its batch.
 int serve_group(int n, int Nm) { return (int)std::min<int64_t>(Nm, ceil_to(n, 16)); }
 
-// Workspace of one batch: per N group the Newton state (tile shapes of a same-N batch of that
-// size) and, with pressure, the pressure partial sums.
+// Tile shape of a served group of size N: the row split a single 64-request tile gets by
+// default, whatever the batch size and whatever the tuning table holds. The partial sums of
+// A(mu) u (and of the pressure right-hand side) are then added in the same order for a
+// request alone and in any mix, so its result is the same bit for bit.
+Tune serve_tune(int N) {
+  Tune t;
+  t.nsplit = default_nsplit(rb::kTile, N * N);
+  t.lu_lds = false;
+  return t;
+}
+int serve_press_nsplit(int N, int Np) { return default_nsplit(rb::kTile, Np * N); }
+
+// Workspace of one batch: per N group the Newton state and, with pressure, the pressure
+// partial sums.
 size_t batch_bytes(rb_server* v, const std::vector<std::pair<int, int>>& groups) {
   size_t b = 0;
   for (auto& g : groups) {
-    const int N = g.first;
+    const int N = g.first, Np = v->s->Np;
     const int64_t Bp = ceil_to(g.second, rb::kTile);
-    const Tune t = tune_for(v->c, v->set, N, v->o.precision, Bp);
-    b += solve_bytes(v->s, N, Bp, t.nsplit, v->o.precision);
-    if (v->o.pressure) b += (size_t)ceil_to((int64_t)pressure_bytes(g.second, N, v->s->Np), 256);
+    b += solve_bytes(v->s, N, Bp, serve_tune(N).nsplit, v->o.precision);
+    if (v->o.pressure)
+      b += (size_t)ceil_to((int64_t)pressure_bytes(g.second, N, Np, serve_press_nsplit(N, Np)),
+                           256);
   }
   return b;
 }
@@ -1412,7 +1482,7 @@ int launch_batch(rb_server* v, Lane& L) {
     const int64_t Bp = ceil_to(n, rb::kTile);
     Pack* pk;
     if (int rc = solve_pack_f64(c, s, N, &pk)) return rc;
-    const Tune t = tune_for(c, v->set, N, o.precision, Bp);
+    const Tune t = serve_tune(N);
     rb::NewtonF64Args a =
         make_args(s, pk, N, n, Nm, o, ta + (int64_t)r0 * s->Q, tc + (int64_t)r0 * s->Qc,
                   tf + (int64_t)r0 * s->Qf, nullptr, nullptr, u + (int64_t)r0 * Nm, it + r0,
@@ -1423,9 +1493,10 @@ int launch_batch(rb_server* v, Lane& L) {
       if (int rc = enqueue_pressure(c, s, n, N, Np, Nm, Np, ta + (int64_t)r0 * s->Q,
                                     tc + (int64_t)r0 * s->Qc, tf + (int64_t)r0 * s->Qf,
                                     tb + (int64_t)r0 * s->Qb, u + (int64_t)r0 * Nm,
-                                    p + (int64_t)r0 * Np, pst + r0, base, gst))
+                                    p + (int64_t)r0 * Np, pst + r0, base, gst,
+                                    serve_press_nsplit(N, Np)))
         return rc;
-      base += (size_t)ceil_to((int64_t)pressure_bytes(n, N, Np), 256);
+      base += (size_t)ceil_to((int64_t)pressure_bytes(n, N, Np, serve_press_nsplit(N, Np)), 256);
     }
     r0 += n;
   }
@@ -1464,7 +1535,9 @@ void harvest(rb_server* v, Lane& L, bool failed) {
         for (int k = 0; k < Np; ++k) r.p[k] = L.h_p[(size_t)i * Np + k];
     }
     r.latency_ms = std::chrono::duration<double, std::milli>(now - q.t_submit).count();
-    v->lat_ms.push_back(r.latency_ms);
+    r.queue_ms = std::chrono::duration<double, std::milli>(L.t_launch - q.t_submit).count();
+    v->lat.add(r.latency_ms);
+    v->wait.add(r.queue_ms);
     v->results.push_back(r);
   }
   v->completed += (long long)L.batch.size();
@@ -1483,7 +1556,9 @@ void bad_request(rb_server* v, const Pending& q) {
   r.status = RB_ST_BADN;
   r.pstatus = RB_ST_BADN;
   r.latency_ms = std::chrono::duration<double, std::milli>(Clock::now() - q.t_submit).count();
-  v->lat_ms.push_back(r.latency_ms);
+  r.queue_ms = r.latency_ms;
+  v->lat.add(r.latency_ms);
+  v->wait.add(r.queue_ms);
   v->results.push_back(r);
   ++v->completed;
 }
@@ -1526,7 +1601,6 @@ void serve(rb_server* v) {
         }
         return g;
       };
-      std::lock_guard<std::mutex> ck(v->c->mu);   // tuning table, workspaces, launches
       size_t n = take.size();
       size_t need = batch_bytes(v, groups_of(take, n));
       const size_t budget = v->o.hbm_budget_bytes;
@@ -1545,11 +1619,23 @@ void serve(rb_server* v) {
       v->inflight += need;
       v->inflight_peak = std::max(v->inflight_peak, v->inflight);
       ++v->batches;
-      const int rc = launch_batch(v, L);
+      L.t_launch = Clock::now();
+      // Launch without the queue lock, so that submitters are not held up for the host time
+      // of the launches; only this thread touches the lanes.
+      lk.unlock();
+      int rc;
+      {
+        std::lock_guard<std::mutex> ck(v->c->mu);   // workspaces, packed operands, launches
+        rc = launch_batch(v, L);
+        if (rc != RB_OK) {
+          for (int k = 0; k < kSubStreams; ++k) (void)hipStreamSynchronize(L.sub[k]);
+          (void)hipStreamSynchronize(L.st);
+        }
+      }
+      const std::string err = rc != RB_OK ? g_err : std::string();
+      lk.lock();
       if (rc != RB_OK) {
-        v->error = g_err;
-        for (int k = 0; k < kSubStreams; ++k) (void)hipStreamSynchronize(L.sub[k]);
-        (void)hipStreamSynchronize(L.st);
+        v->error = err;
         harvest(v, L, true);
       }
       progress = true;
@@ -1721,14 +1807,11 @@ int rb_server_stats(rb_server* v, rb_server_counters* st) {
   st->submitted = v->submitted;
   st->completed = v->completed;
   st->batches = v->batches;
-  if (!v->lat_ms.empty()) {
-    std::vector<double> l = v->lat_ms;
-    std::sort(l.begin(), l.end());
-    auto q = [&](double f) { return l[std::min(l.size() - 1, (size_t)(f * (l.size() - 1) + 0.5))]; };
-    st->p50_ms = q(0.50);
-    st->p99_ms = q(0.99);
-    st->max_ms = l.back();
-  }
+  st->p50_ms = v->lat.quantile(0.50);
+  st->p99_ms = v->lat.quantile(0.99);
+  st->max_ms = v->lat.maxv;
+  st->p50_queue_ms = v->wait.quantile(0.50);
+  st->p99_queue_ms = v->wait.quantile(0.99);
   st->mean_batch = v->batches ? (double)(v->completed) / v->batches : 0.0;
   st->first_submit_s = v->first_submit_s;
   st->last_done_s = v->last_done_s;

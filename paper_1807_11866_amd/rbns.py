@@ -61,14 +61,16 @@ class Request(ct.Structure):
 class Result(ct.Structure):
     _fields_ = [("ticket", ct.c_longlong), ("tag", ct.c_longlong), ("N", ct.c_int),
                 ("status", ct.c_int), ("iters", ct.c_int), ("pstatus", ct.c_int),
-                ("latency_ms", ct.c_double), ("u", ct.c_double * RB_MAX_N),
+                ("latency_ms", ct.c_double), ("queue_ms", ct.c_double),
+                ("u", ct.c_double * RB_MAX_N),
                 ("p", ct.c_double * RB_MAX_NP)]
 
 
 class ServerStats(ct.Structure):
     _fields_ = [("submitted", ct.c_longlong), ("completed", ct.c_longlong),
                 ("batches", ct.c_longlong), ("p50_ms", ct.c_double), ("p99_ms", ct.c_double),
-                ("max_ms", ct.c_double), ("mean_batch", ct.c_double),
+                ("max_ms", ct.c_double), ("p50_queue_ms", ct.c_double),
+                ("p99_queue_ms", ct.c_double), ("mean_batch", ct.c_double),
                 ("first_submit_s", ct.c_double), ("last_done_s", ct.c_double),
                 ("hbm_inflight_peak", ct.c_size_t), ("error", ct.c_char * 256)]
 
@@ -404,12 +406,13 @@ class Server:
 
     def poll(self):
         """Finished results as a list of dicts (ticket, tag, N, status, iters, pstatus,
-        latency_ms, u (first N entries), p)."""
+        latency_ms, queue_ms, u (first N entries), p)."""
         out = []
         for r in self.poll_array():
             out.append(dict(ticket=int(r["ticket"]), tag=int(r["tag"]), N=int(r["N"]),
                             status=int(r["status"]), iters=int(r["iters"]),
                             pstatus=int(r["pstatus"]), latency_ms=float(r["latency_ms"]),
+                            queue_ms=float(r["queue_ms"]),
                             u=r["u"][:int(r["N"])].copy(), p=r["p"].copy()))
         return out
 

@@ -3,8 +3,8 @@
 A request's result must not depend on the batch it was served in: the same request is
 served alone and in the middle of a stream of other requests of mixed basis size, and the
 two results must agree bit for bit (each request's arithmetic is independent of the other
-columns of its tile, and the tile shapes depend only on N and the batch size class). Every
-result is also checked against the FP64 oracle at the request's own N.
+columns of its tile, and a served group's tile shapes depend on its N alone, never on the
+batch size). Every result is also checked against the FP64 oracle at the request's own N.
 """
 
 import time
@@ -43,9 +43,10 @@ def _collect(srv, n, timeout=60.0):
     return got
 
 
-def _alone_and_in_mix(R, O, ts, cfg, prec, refine, tol_u, pressure):
+def _alone_and_in_mix(R, O, ts, cfg, prec, refine, tol_u, pressure, max_batch=256, lanes=3,
+                      burst=50):
     s = R.Solver(ts)
-    srv = R.Server(s, precision=prec, refine_steps=refine, max_batch=256, lanes=3,
+    srv = R.Server(s, precision=prec, refine_steps=refine, max_batch=max_batch, lanes=lanes,
                    pressure=pressure)
     try:
         mu = draw_mu(cfg, 600, seed_offset=31)
@@ -54,9 +55,9 @@ def _alone_and_in_mix(R, O, ts, cfg, prec, refine, tol_u, pressure):
         t_alone = srv.submit(mu[x, 0], mu[x, 1], Nreq[x], tags=[-1])
         alone = _collect(srv, 1)[t_alone[0]]
         tickets = []
-        for k in range(0, 600, 50):                       # arrivals in bursts
-            tickets.extend(srv.submit(mu[k:k + 50, 0], mu[k:k + 50, 1], Nreq[k:k + 50],
-                                      tags=np.arange(k, k + 50)))
+        for k in range(0, 600, burst):                    # arrivals in bursts
+            tickets.extend(srv.submit(mu[k:k + burst, 0], mu[k:k + burst, 1],
+                                      Nreq[k:k + burst], tags=np.arange(k, k + burst)))
             time.sleep(0.0005)
         got = _collect(srv, 600)
         mix = got[tickets[x]]
@@ -66,7 +67,8 @@ def _alone_and_in_mix(R, O, ts, cfg, prec, refine, tol_u, pressure):
             assert np.array_equal(alone["p"], mix["p"])
         st = srv.stats()
         assert st["completed"] == 601 and st["submitted"] == 601 and st["error"] == ""
-        assert 0 < st["p50_ms"] <= st["p99_ms"] <= st["max_ms"]
+        assert 0 < st["p50_ms"] <= st["p99_ms"] <= st["max_ms"] * 1.006
+        assert 0 <= st["p50_queue_ms"] <= st["p99_queue_ms"] <= st["p99_ms"] * 1.006
         assert st["batches"] >= 2                         # the stream was batched, not queued whole
         # every result against the oracle at its own N
         r = O.solve_batch(O.OracleSet(ts), mu, Nreq=Nreq, pressure_np=ts.Np if pressure else 0)
@@ -87,6 +89,16 @@ def test_server_fp64_alone_equals_in_mix(oracle_lib, R):
     cfg = dict(get_config("batched_n50"), N_choices=(10, 25, 40, 50))
     ts = make_tensor_set(get_config("batched_n50"))
     _alone_and_in_mix(R, oracle_lib, ts, cfg, R.RB_PREC_F64, 0, 1e-10, pressure=True)
+
+
+def test_server_fp64_alone_equals_in_large_mixed_batch(oracle_lib, R):
+    """One burst of 600 requests with max_batch 4096: every size-class group of the batch
+    holds more than 64 requests (several tiles), where the default row split of a one-off
+    batch would differ from a lone request's; the served result must still be identical."""
+    cfg = dict(get_config("batched_n50"), N_choices=(10, 25, 40, 50))
+    ts = make_tensor_set(get_config("batched_n50"))
+    _alone_and_in_mix(R, oracle_lib, ts, cfg, R.RB_PREC_F64, 0, 1e-10, pressure=True,
+                      max_batch=4096, lanes=1, burst=600)
 
 
 @pytest.mark.parametrize("prec,refine", [("BF16", 4), ("BF16X3", 1)])
