@@ -166,6 +166,32 @@ int rb_solve_batch(rb_ctx *ctx, int set, int B, int N, int ldu, const double *th
                    int *status, void *hip_stream);
 
 /*
+ * rb_solve_batch_noalloc: rb_solve_batch for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc. Same
+ * arguments, same kernels and tile shapes, same results as rb_solve_batch. The Newton state
+ * (Jacobians, iterates, partial sums, flags) lives in one static device array of
+ * RB_NOALLOC_SCRATCH_BYTES per device, held from library load to process exit, instead of a
+ * per-stream workspace; the call allocates nothing (no hipMalloc / hipFree / library
+ * allocation, no kernel-timing events). The state is initialised by the call's first kernel,
+ * so nothing carries over between calls.
+ * Every call on one device shares that device's array: calls that overlap on a device (other
+ * streams, other contexts, other threads) race and corrupt each other's results. Serialise
+ * them (one stream, or events) and leave this entry point out of concurrent use.
+ * Preconditions: the packed contraction operands for (N, precision) exist; rb_load_tensors
+ * builds them for the set's own N in FP64, and any earlier rb_solve_batch or rb_autotune call
+ * at (N, precision) builds the others.
+ * Errors: as rb_solve_batch; RB_E_NOMEM when the batch's state exceeds the array (about 24 KB
+ * per request at N = 50 in FP64, so B <= 2700 there; 64-request tiles), RB_E_STATE when the
+ * packed operands are missing.
+ */
+#define RB_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int rb_solve_batch_noalloc(rb_ctx *ctx, int set, int B, int N, int ldu, const double *theta_a,
+                           const double *theta_c, const double *theta_f,
+                           const double *f_override, const double *u0,
+                           const rb_solve_opts *opts, double *u, int *iters, int *status,
+                           void *hip_stream);
+
+/*
  * rb_solve_uneven: like rb_solve_batch, but each request b has its own basis size N[b]
  * (device int [B]; the nested basis of size N[b] is the leading block of the set's tensors);
  * rows of u0 / f_override / u have stride ldu >= the set's N. Not part of the paper: a

@@ -23,6 +23,13 @@
 #include "../../include/rbns.h"
 #include "rb_launch.hpp"
 
+// Device scratch of rb_solve_batch_noalloc: the Newton state of one call lives here instead of
+// in a per-stream workspace, so that entry point allocates nothing. Each device holds its own
+// copy for the life of the process. In host code `scratch` names a host-side stand-in, never
+// the device memory: kernels and copies get the per-device address that rb_create looks up
+// with hipGetSymbolAddress (scratch_ptr below).
+static __device__ __align__(256) char scratch[RB_NOALLOC_SCRATCH_BYTES];
+
 namespace {
 
 thread_local std::string g_err;
@@ -95,6 +102,7 @@ struct TimedLaunch {
 
 struct rb_ctx {
   int device = 0;
+  char* scratch = nullptr;              // this device's address of `scratch`
   size_t budget = 0, used = 0;
   std::vector<std::unique_ptr<Set>> sets;
   std::map<void*, Workspace> ws;
@@ -720,6 +728,26 @@ int ensure_streams(rb_ctx* c, int n) {
   return RB_OK;
 }
 
+// Device address of `scratch` on `device` (which must be current): looked up once per device
+// and kept, since every device holds the array at its own address.
+std::mutex g_scratch_mu;
+std::map<int, char*> g_scratch_ptr;
+
+int scratch_address(int device, char** out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(device);
+  if (it == g_scratch_ptr.end()) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(RB_E_DEVICE, "rb_create: no device address for the scratch array: %s",
+                  hipGetErrorString(e));
+    it = g_scratch_ptr.emplace(device, (char*)p).first;
+  }
+  *out = it->second;
+  return RB_OK;
+}
+
 constexpr int kBranches = 4;      // concurrent bucket chains inside an uneven-batch graph
 constexpr size_t kGraphCache = 16;
 
@@ -737,8 +765,11 @@ int rb_create(int device, size_t hbm_budget_bytes, rb_ctx** out) {
   if (device < 0 || device >= n)
     return fail(RB_E_INVAL, "rb_create: device %d not in [0, %d)", device, n);
   HIP_TRY(hipSetDevice(device));
+  char* sp = nullptr;
+  if (int rc = scratch_address(device, &sp)) return rc;
   rb_ctx* c = new rb_ctx;
   c->device = device;
+  c->scratch = sp;
   c->budget = hbm_budget_bytes;
   if (const char* v = getenv("RB_LU_BCAST")) c->lu_lds = (strcmp(v, "lds") == 0);
   if (const char* v = getenv("RB_AUTOTUNE")) c->autotune = (strcmp(v, "0") != 0);
@@ -882,6 +913,55 @@ int rb_solve_batch(rb_ctx* c, int set, int B, int N, int ldu, const double* ta,
   rb::NewtonF64Args a = make_args(s, pk, N, B, ldu, o, ta, tc, tf, fover, u0, u, iters, status,
                                   region, t.nsplit);
   return enqueue_solve(c, s, a, o, t, region, (hipStream_t)stream);
+}
+
+int rb_solve_batch_noalloc(rb_ctx* c, int set, int B, int N, int ldu, const double* ta,
+                           const double* tc, const double* tf, const double* fover,
+                           const double* u0, const rb_solve_opts* opts, double* u, int* iters,
+                           int* status, void* stream) {
+  if (!c) return fail(RB_E_INVAL, "rb_solve_batch_noalloc: NULL context");
+  Set* s = get_set(c, set);
+  if (!s) return fail(RB_E_INVAL, "rb_solve_batch_noalloc: unknown set %d", set);
+  if (B < 0) return fail(RB_E_INVAL, "rb_solve_batch_noalloc: B=%d", B);
+  if (N < 1 || N > s->N)
+    return fail(RB_E_INVAL, "rb_solve_batch_noalloc: N=%d outside [1, %d]", N, s->N);
+  if (ldu < N) return fail(RB_E_INVAL, "rb_solve_batch_noalloc: ldu=%d < N=%d", ldu, N);
+  rb_solve_opts o = {1e-12, 10, RB_PREC_F64, 1};
+  if (opts) o = *opts;
+  if (int rc = check_opts("rb_solve_batch_noalloc", o)) return rc;
+  if (o.precision == RB_PREC_F64 && N > RB_MAX_N_F64)
+    return fail(RB_E_UNSUPPORTED, "rb_solve_batch_noalloc: FP64 solves take N <= %d (N=%d)",
+                RB_MAX_N_F64, N);
+  if (B == 0) return RB_OK;
+  if (!ta || !tc || (!tf && !fover) || !u || !iters || !status)
+    return fail(RB_E_INVAL, "rb_solve_batch_noalloc: NULL array");
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (int rc = use_device(c)) return rc;
+  // The packed operands are built (allocated) by rb_load_tensors for the set's N in FP64 and
+  // by the first rb_solve_batch / rb_autotune at any other (N, precision); this entry point
+  // only uses them.
+  auto pf = s->solve_f64.find(N);
+  if (pf == s->solve_f64.end() ||
+      (o.precision != RB_PREC_F64 && !s->solve_lp.count(std::make_pair(N, o.precision))))
+    return fail(RB_E_STATE,
+                "rb_solve_batch_noalloc: no packed operand for N=%d, precision %d yet (one "
+                "rb_solve_batch call at that N and precision builds it)", N, o.precision);
+  const int64_t Bp = ceil_to(B, rb::kTile);
+  const Tune t = tune_for(c, set, N, o.precision, Bp);
+  const size_t need = solve_bytes(s, N, Bp, t.nsplit, o.precision);
+  if (need > (size_t)RB_NOALLOC_SCRATCH_BYTES)
+    return fail(RB_E_NOMEM,
+                "rb_solve_batch_noalloc: B=%d at N=%d needs %zu bytes of scratch, the device "
+                "array holds %zu", B, N, need, (size_t)RB_NOALLOC_SCRATCH_BYTES);
+  char* region = c->scratch;
+  rb::NewtonF64Args a = make_args(s, &pf->second, N, B, ldu, o, ta, tc, tf, fover, u0, u,
+                                  iters, status, region, t.nsplit);
+  // no kernel timing here: its events are created on demand
+  const bool timing = c->timing;
+  c->timing = false;
+  const int rc = enqueue_solve(c, s, a, o, t, region, (hipStream_t)stream);
+  c->timing = timing;
+  return rc;
 }
 
 int rb_autotune(rb_ctx* c, int set, int B, int N, const double* ta, const double* tc,

@@ -19,7 +19,7 @@ RB_ST_CONVERGED, RB_ST_MAXIT, RB_ST_SINGULAR, RB_ST_NONFINITE, RB_ST_BADN = 0, 1
 RB_PREC_F64, RB_PREC_F32, RB_PREC_BF16, RB_PREC_BF16X3 = 0, 1, 2, 3
 
 EXPORTED = ("rb_create", "rb_destroy", "rb_last_error", "rb_hbm_used", "rb_load_tensors",
-            "rb_theta", "rb_solve_batch", "rb_solve_uneven", "rb_autotune", "rb_tuned_config",
+            "rb_theta", "rb_solve_batch", "rb_solve_batch_noalloc", "rb_solve_uneven", "rb_autotune", "rb_tuned_config",
             "rb_recover_pressure", "rb_recover_pressure_uneven", "rb_server_start", "rb_server_submit", "rb_server_poll",
             "rb_server_stats", "rb_server_stop", "rb_timing_enable", "rb_timing_read")
 RB_ST_FAILED = 5
@@ -97,6 +97,7 @@ def load(path=None):
     lib.rb_theta.argtypes = [_vp, ct.c_int, ct.c_int] + [_vp] * 5 + [_vp]
     lib.rb_solve_batch.argtypes = ([_vp, ct.c_int, ct.c_int, ct.c_int, ct.c_int] + [_vp] * 5 +
                                    [ct.POINTER(SolveOpts)] + [_vp] * 3 + [_vp])
+    lib.rb_solve_batch_noalloc.argtypes = lib.rb_solve_batch.argtypes
     lib.rb_solve_uneven.argtypes = ([_vp, ct.c_int, ct.c_int, _vp, ct.c_int] + [_vp] * 5 +
                                     [ct.POINTER(SolveOpts)] + [_vp] * 3 + [_vp])
     lib.rb_autotune.argtypes = ([_vp, ct.c_int, ct.c_int, ct.c_int] + [_vp] * 3 +
@@ -201,6 +202,14 @@ def rb_solve_batch(ctx, set_id, B, N, ldu, theta_a, theta_c, theta_f, f_override
                                  _ptr(theta_c), _ptr(theta_f), _ptr(f_override), _ptr(u0),
                                  ct.byref(opts) if opts is not None else None, _ptr(u),
                                  _ptr(iters), _ptr(status), _stream(stream)))
+
+
+def rb_solve_batch_noalloc(ctx, set_id, B, N, ldu, theta_a, theta_c, theta_f, f_override, u0,
+                           opts, u, iters, status, stream=None):
+    _check(load().rb_solve_batch_noalloc(ctx, set_id, int(B), int(N), int(ldu), _ptr(theta_a),
+                                         _ptr(theta_c), _ptr(theta_f), _ptr(f_override),
+                                         _ptr(u0), ct.byref(opts) if opts is not None else None,
+                                         _ptr(u), _ptr(iters), _ptr(status), _stream(stream)))
 
 
 def rb_solve_uneven(ctx, set_id, B, N, ldu, theta_a, theta_c, theta_f, f_override, u0, opts,
