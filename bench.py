@@ -362,6 +362,11 @@ def main():
                     help="tensor format of the serve_n150 workload")
     ap.add_argument("--serve-lanes", type=int, default=1,
                     help="server lanes (batches in flight) of the serve_n150 workload")
+    ap.add_argument("--coupled", type=int, default=1,
+                    help="time the coupled stabilised (naive) solver against the block method "
+                         "at m = 10, 20, 30 (0 = skip)")
+    ap.add_argument("--reconstruct", type=int, default=1,
+                    help="time the combined-basis pressure reconstruction (0 = skip)")
     ap.add_argument("--autotune", action="store_true",
                     help="run the library's autotuner on the batch before the warm-up")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -485,6 +490,106 @@ def main():
         extra["max_rel_err_u"] = float(rel_err(u, ref["u"]).max())
         extra["max_rel_err_p"] = float(rel_err(p, ref["p"]).max())
         extra["checked_requests"] = int(len(idx))
+
+    # ---- pressure reconstruction from a combined basis (p = Pc u) -------------------------
+    # Offline step with the library itself: the 15 x 15 Gauss training ensemble solved and its
+    # pressure recovered on the GPU, Pc = P pinv(U) (minimum-norm snapshot coefficients, the
+    # paper's second combined-basis construction). Online: one matrix-vector product per
+    # request, timed on the same batch as the headline, error against the recovered pressure.
+    if args.reconstruct:
+        from rbinputs.synth import gauss_grid_mu
+        mtr = gauss_grid_mu(cfg)
+        thr = s.theta(torch.as_tensor(mtr, device=dev))
+        otr = s.solve(thr, tol=cfg["tol"], max_iter=cfg["max_iter"], stream=stream)
+        ptr = s.pressure(thr, otr["u"], stream=stream)
+        torch.cuda.synchronize()
+        Ut, Pt = otr["u"].cpu().numpy(), ptr["p"].cpu().numpy()
+        Pc = Pt.T @ np.linalg.pinv(Ut.T, rcond=1e-8)
+        dPc = torch.as_tensor(Pc, device=dev)
+        prc = torch.empty(B, Np, **f64)
+        for _ in range(3):
+            s.reconstruct(dPc, out["u"], out=prc, stream=stream)
+        torch.cuda.synchronize()
+        rbns.rb_timing_enable(s.ctx, True)
+        nrc = 50
+        tr0 = time.perf_counter()
+        for _ in range(nrc):
+            s.reconstruct(dPc, out["u"], out=prc, stream=stream)
+        torch.cuda.synchronize()
+        tr1 = time.perf_counter()
+        rbns.rb_timing_enable(s.ctx, False)
+        kms, kn = rbns.rb_timing_read(s.ctx, "reconstruct")
+        pr = prc.cpu().numpy()
+        prv = pout["p"].cpu().numpy()
+        erc = rel_err(pr, prv)
+        extra["reconstructed"] = dict(
+            value=B * nrc / (tr1 - tr0), unit="pressures/s", kernel_us=1e3 * kms / max(kn, 1),
+            recovery_kernel_us=1e3 * kern["pressure"]["avg_launch_ms"],
+            training_parameters=int(len(mtr)),
+            rel_diff_vs_recovered_p50=float(np.median(erc)),
+            rel_diff_vs_recovered_max=float(erc.max()))
+        if ref is not None:
+            extra["reconstructed"]["max_rel_err_p_vs_oracle_recovery"] = float(
+                rel_err(pr[idx], ref["p"]).max())
+        log(f"[bench] reconstruction: {extra['reconstructed']['kernel_us']:.1f} us per batch, "
+            f"max rel. difference from recovery {erc.max():.2e}")
+
+    # ---- the paper's naive solver: Newton on the coupled stabilised system (eqn block) -----
+    # Velocity, supremizer and pressure spaces of equal size m (the paper's comparison, with
+    # 3m unknowns) against the block method (velocity-only Newton at m + pressure recovery),
+    # same library, same batch of parameters, same stopping rule, FP64. Pressure form with
+    # the identity weight only (B_vp = 0), so both reach the same (u, p).
+    if args.coupled:
+        from rbinputs.synth import make_coupled_set
+        cfg1 = get_config(args.workload, Qb=1)
+        base1 = make_tensor_set(cfg1)
+        mu_c = torch.as_tensor(mu_h, device=dev)
+        cres = {}
+        for m in (10, 20, 30):
+            ts_b = base1.leading(m, m)
+            ts_c = make_coupled_set(cfg1, m, m)
+            sb, sc = rbns.Solver(ts_b, device=0), rbns.Solver(ts_c, device=0)
+            thb = sb.theta(mu_c)
+            thc = dict(ta=torch.cat([thb["ta"], torch.ones_like(thb["ta"][:, :1])], 1).contiguous(),
+                       tc=thb["tc"], tf=thb["tf"])
+            ob = dict(u=torch.empty(B, m, **f64), iters=torch.empty(B, dtype=torch.int32, device=dev),
+                      status=torch.empty(B, dtype=torch.int32, device=dev))
+            pb = dict(p=torch.empty(B, m, **f64), pstatus=torch.empty(B, dtype=torch.int32, device=dev))
+            oc = dict(u=torch.empty(B, 3 * m, **f64), iters=torch.empty(B, dtype=torch.int32, device=dev),
+                      status=torch.empty(B, dtype=torch.int32, device=dev))
+
+            def blk():
+                sb.solve(thb, out=ob, tol=cfg["tol"], max_iter=cfg["max_iter"], stream=stream)
+                sb.pressure(thb, ob["u"], out=pb, stream=stream)
+
+            def nai():
+                sc.solve(thc, out=oc, tol=cfg["tol"], max_iter=cfg["max_iter"], stream=stream)
+            tms = {}
+            for name, fn in (("block", blk), ("naive", nai)):
+                for _ in range(2):
+                    fn()
+                torch.cuda.synchronize()
+                nrep = 5
+                t0c = time.perf_counter()
+                for _ in range(nrep):
+                    fn()
+                torch.cuda.synchronize()
+                tms[name] = (time.perf_counter() - t0c) / nrep
+            x = oc["u"].cpu().numpy()
+            ub, pp = ob["u"].cpu().numpy(), pb["p"].cpu().numpy()
+            cres[str(m)] = dict(unknowns_block=m, unknowns_naive=3 * m,
+                                block_solves_s=B / tms["block"], naive_solves_s=B / tms["naive"],
+                                speedup_block_vs_naive=tms["naive"] / tms["block"],
+                                max_rel_diff_u=float(rel_err(x[:, :m], ub).max()),
+                                max_rel_diff_p=float(rel_err(x[:, 2 * m:], pp).max()),
+                                max_abs_s=float(np.abs(x[:, m:2 * m]).max()),
+                                naive_status_hist=np.bincount(oc["status"].cpu().numpy(),
+                                                              minlength=5).tolist())
+            log(f"[bench] m={m}: block {B / tms['block']:.4g} solves/s, naive {B / tms['naive']:.4g} "
+                f"solves/s ({tms['naive'] / tms['block']:.1f}x)")
+            sb.close()
+            sc.close()
+        extra["coupled_vs_block"] = cres
 
     # ---- plain per-solve GPU path: the same library, one request per call ------------------
     if args.plain > 0:

@@ -104,6 +104,21 @@ typedef struct {
 #define RB_MAX_QF   2
 #define RB_MAX_QB   2
 
+/* Variants of the FP64 dense solve of the Newton and pressure systems (one system per
+ * wavefront up to 64 unknowns): one row per lane with the pivot row broadcast by readlane or
+ * through LDS, or the system in matrix-core tiles with panel updates on MFMA (N <=
+ * RB_LU_MFMA_MAX_N; larger systems fall back to readlane). RB_LU_AUTO (the default) takes the
+ * matrix-core solve up to RB_LU_AUTO_MFMA_N unknowns and readlane beyond, the faster of the
+ * two on MI355X at 4096 systems (N = 30: 39 vs 53 us per launch; N = 50: 129 vs 97 us). The
+ * environment variable RB_LU=auto|readlane|lds|mfma sets it for a new context, and the
+ * autotuner times the variants per batch shape. */
+#define RB_LU_READLANE   0
+#define RB_LU_LDS        1
+#define RB_LU_MFMA       2
+#define RB_LU_AUTO       3
+#define RB_LU_MFMA_MAX_N 63
+#define RB_LU_AUTO_MFMA_N 31
+
 /*
  * rb_create: make a context on HIP device `device`. hbm_budget_bytes caps the device memory
  * the context may hold (resident tensors + workspaces); 0 means no cap.
@@ -235,7 +250,7 @@ int rb_recover_pressure_uneven(rb_ctx *ctx, int set, int B, const int *N, int Np
  * the default number of row splits per 64-request tile of the contraction, and (FP64,
  * N <= 64) the pivot-row broadcast of the LU (readlane or LDS). Synchronous; produces no
  * solution.
- * rb_tuned_config: the shape in use for such a batch, lu_variant 0 = readlane, 1 = LDS.
+ * rb_tuned_config: the shape in use for such a batch, lu_variant one of RB_LU_*.
  * Defaults when never tuned: readlane, and 8 row splits (one per XCD) for batches that fill
  * the chip, up to 64 for small ones (about 512 workgroups, at least 4 row blocks a split).
  * Errors: RB_E_INVAL, RB_E_UNSUPPORTED (FP64 beyond RB_MAX_N_F64), RB_E_DEVICE.
@@ -259,6 +274,21 @@ int rb_recover_pressure(rb_ctx *ctx, int set, int B, int N, int Np, int ldu, int
                         const double *theta_a, const double *theta_c, const double *theta_f,
                         const double *theta_b, const double *u, double *p, int *status,
                         void *hip_stream);
+
+/*
+ * rb_reconstruct_pressure: pressure from a combined velocity-pressure basis (Section 4.2, the
+ * second construction after eqn z_c): each reduced velocity function carries a pressure part
+ * made of the same snapshot combination, so p = Pc u for every request,
+ *   p[b][i] = sum_{j < N} Pc[i][j] u[b][j],  i < Np   (entries Np <= i < ldp set to 0).
+ * Device inputs: Pc [Np][ldpc] (pressure-basis coefficients of the pressure parts of the
+ * first N velocity functions; nested bases use its leading columns), u [B][ldu]. Device
+ * output: p [B][ldp]. Unlike rb_recover_pressure this presumes that the pressure depends
+ * linearly on the velocity (the paper's remark on linearity); it needs no tensor set.
+ * Errors: RB_E_INVAL (NULL, sizes: 1 <= N <= RB_MAX_N, 1 <= Np <= RB_MAX_NP, ldpc, ldu >= N,
+ * ldp >= Np), RB_E_DEVICE. B == 0 is a no-op.
+ */
+int rb_reconstruct_pressure(rb_ctx *ctx, int B, int N, int Np, const double *Pc, int ldpc,
+                            const double *u, int ldu, double *p, int ldp, void *hip_stream);
 
 /* ------------------------------------------------------------------ serving --------- */
 /*
@@ -346,7 +376,8 @@ int rb_server_stop(rb_server *srv);
  * Errors: RB_E_INVAL (unknown family), RB_E_DEVICE.
  */
 int rb_timing_enable(rb_ctx *ctx, int enable);
-/* (family "residual": the FP64 residual contraction of the mixed-precision refinement) */
+/* (family "residual": the FP64 residual contraction of the mixed-precision refinement;
+ *  family "reconstruct": rb_reconstruct_pressure) */
 int rb_timing_read(rb_ctx *ctx, const char *family, double *total_ms, int *launches);
 
 #ifdef __cplusplus

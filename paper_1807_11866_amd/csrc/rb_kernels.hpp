@@ -591,8 +591,9 @@ struct PressureF64Args {
   const double* tb;        // [B][Qb]
   const double* BpT;       // [Qb][Npm][Npm] transposed: BpT[q][c][i] = B_q[i][c]
   const double* Fs;        // [Qf][Npm]
-  const double* part;      // [nsplit][Bp][NPP] partial sums of A_sv u + C_sv(u,u)
+  const double* part;      // [nsplit][Bp][ldpart] partial sums of A_sv u + C_sv(u,u)
   int nsplit;
+  int ldpart;              // row stride of the partial sums (the row bucket NPP)
   double* p;               // [B][ldp]
   int* status;             // [B]
 };

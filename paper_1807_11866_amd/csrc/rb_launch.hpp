@@ -16,8 +16,9 @@ namespace launch {
 int contract_f64(int mode, const ContractArgs& g, hipStream_t st);
 // FP64 Newton LU: NP <= 64 one wavefront per system, NP > 64 (multiple of 8, <= 96) one
 // workgroup per system.
-int lu_f64(int NP, const NewtonF64Args& a, int it, bool lds_bcast, hipStream_t st);
-int plu_f64(int NPP, const PressureF64Args& a, bool lds_bcast, hipStream_t st);
+// `variant` is one of RB_LU_*; RB_LU_MFMA beyond RB_LU_MFMA_MAX_N falls back to readlane.
+int lu_f64(int NP, const NewtonF64Args& a, int it, int variant, hipStream_t st);
+int plu_f64(int NPP, const PressureF64Args& a, int variant, hipStream_t st);
 // Low-precision contraction, prec = RB_PREC_F32 (KT even <= 64 or a multiple of 4 <= 152),
 // RB_PREC_BF16 (KT <= 20) or RB_PREC_BF16X3 (KT <= 20).
 int contract_lp(int prec, int KT, const ContractLpArgs& g, hipStream_t st);
@@ -29,6 +30,8 @@ int contract_f64_jac(const ContractArgs& g, hipStream_t st);
 int contract_f64_press(const ContractArgs& g, hipStream_t st);
 int contract_f64_resid(const ContractArgs& g, hipStream_t st);
 int lu_f64_mw(int NP, const NewtonF64Args& a, int it, hipStream_t st);
+int lu_f64_mfma(const NewtonF64Args& a, int it, hipStream_t st);
+int plu_f64_mfma(const PressureF64Args& a, hipStream_t st);
 int lu_lp_mw(int NP, bool refine, const LpNewtonArgs& a, int it, hipStream_t st);
 int lu_lp_mw_wide(int NP, bool refine, const LpNewtonArgs& a, int it, hipStream_t st);
 int contract_lp_f32_wide(int KT, const ContractLpArgs& g, hipStream_t st);

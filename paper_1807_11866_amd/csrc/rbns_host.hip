@@ -22,6 +22,7 @@
 
 #include "../../include/rbns.h"
 #include "rb_launch.hpp"
+#include "rb_reconstruct.hpp"
 
 // Device scratch of rb_solve_batch_noalloc: the Newton state of one call lives here instead of
 // in a per-stream workspace, so that entry point allocates nothing. Each device holds its own
@@ -82,7 +83,7 @@ struct Workspace {
 // the contraction and the pivot-row broadcast of the one-wavefront FP64 LU.
 struct Tune {
   int nsplit = 8;
-  bool lu_lds = false;
+  int lu = RB_LU_AUTO;
 };
 
 // A captured uneven-batch graph and the shape it was captured for.
@@ -108,7 +109,7 @@ struct rb_ctx {
   std::map<void*, Workspace> ws;
   std::mutex mu;
   bool timing = false;
-  bool lu_lds = false;                  // pivot-row broadcast through LDS instead of readlane
+  int lu = RB_LU_AUTO;                  // LU variant of the FP64 solves (RB_LU_*)
   std::vector<TimedLaunch> timed;       // recorded, not yet read
   std::vector<hipEvent_t> event_pool;
   // autotuner results: (set, N, precision, batch size class) -> tile shape
@@ -356,8 +357,10 @@ size_t solve_bytes(const Set* s, int N, int64_t Bp, int nsplit, int precision) {
   return (size_t)ceil_to((int64_t)b, 256);
 }
 
-enum { FAM_JACOBIAN = 0, FAM_LU = 1, FAM_PRESSURE = 2, FAM_RESIDUAL = 3, FAM_COUNT = 4 };
-const char* const kFamilies[FAM_COUNT] = {"jacobian", "lu", "pressure", "residual"};
+enum { FAM_JACOBIAN = 0, FAM_LU = 1, FAM_PRESSURE = 2, FAM_RESIDUAL = 3, FAM_RECONSTRUCT = 4,
+       FAM_COUNT = 5 };
+const char* const kFamilies[FAM_COUNT] = {"jacobian", "lu", "pressure", "residual",
+                                          "reconstruct"};
 
 hipEvent_t take_event(rb_ctx* c) {
   if (!c->event_pool.empty()) {
@@ -393,7 +396,7 @@ struct LaunchTimer {
 
 // Enqueue a whole batched Newton solve: init, max_iter x (Jacobian kernel, LU kernel),
 // final copy-out. Converged requests are skipped by both kernels through the done flags.
-int enqueue_newton(rb_ctx* c, const rb::NewtonF64Args& a, bool lu_lds, hipStream_t st) {
+int enqueue_newton(rb_ctx* c, const rb::NewtonF64Args& a, int lu, hipStream_t st) {
   const int NP = a.s.NP;
   const int64_t Bp = a.s.Bp;
   rb::ContractArgs g;
@@ -413,7 +416,7 @@ int enqueue_newton(rb_ctx* c, const rb::NewtonF64Args& a, bool lu_lds, hipStream
       if (int rc = launch_rc(rb::launch::contract_f64(rb::kModeJac, g, st), "jacobian")) return rc;
     }
     LaunchTimer t(c, FAM_LU, st);
-    if (int rc = launch_rc(rb::launch::lu_f64(NP, a, it, lu_lds, st), "lu")) return rc;
+    if (int rc = launch_rc(rb::launch::lu_f64(NP, a, it, lu, st), "lu")) return rc;
   }
   hipLaunchKernelGGL(rb::newton_final_kernel, dim3(launch_grid((int64_t)a.B * a.ldu)),
                      dim3(256), 0, st, a);
@@ -531,12 +534,12 @@ int enqueue_pressure(rb_ctx* c, Set* s, int B, int N, int Np, int ldu, int ldp,
   a.tf = tf; a.tb = tb;
   a.BpT = (const double*)s->BpT.p;
   a.Fs = (const double*)s->Fs.p;
-  a.part = g.part; a.nsplit = g.nsplit;
+  a.part = g.part; a.nsplit = g.nsplit; a.ldpart = NPP;
   a.p = p; a.status = status;
   LaunchTimer t(c, FAM_PRESSURE, st);
   if (int rc = launch_rc(rb::launch::contract_f64(rb::kModePressure, g, st), "pressure"))
     return rc;
-  if (int rc = launch_rc(rb::launch::plu_f64(NPP, a, c->lu_lds, st), "pressure lu")) return rc;
+  if (int rc = launch_rc(rb::launch::plu_f64(NPP, a, c->lu, st), "pressure lu")) return rc;
   HIP_TRY(hipGetLastError());
   return RB_OK;
 }
@@ -567,7 +570,7 @@ Tune tune_for(rb_ctx* c, int set, int N, int precision, int64_t Bp) {
   if (it != c->tune.end()) return it->second;
   Tune t;
   t.nsplit = default_nsplit(Bp, N * N);
-  t.lu_lds = c->lu_lds;
+  t.lu = c->lu;
   return t;
 }
 
@@ -605,7 +608,7 @@ rb::NewtonF64Args make_args(Set* s, Pack* pk, int N, int B, int ldu, const rb_so
 
 int enqueue_solve(rb_ctx* c, Set* s, const rb::NewtonF64Args& a, const rb_solve_opts& o,
                   const Tune& t, char* region, hipStream_t st) {
-  if (o.precision == RB_PREC_F64) return enqueue_newton(c, a, t.lu_lds, st);
+  if (o.precision == RB_PREC_F64) return enqueue_newton(c, a, t.lu, st);
   char* lp = region + newton_state_bytes(a.s.Bp, a.s.NP, a.s.mp, a.s.nsplit, a.s.jslices);
   return enqueue_newton_lp(c, s, a, o.precision, o.refine_steps, lp, st);
 }
@@ -667,7 +670,7 @@ int autotune_batch(rb_ctx* c, Set* s, int set, rb::NewtonF64Args a, const rb_sol
   };
   hipLaunchKernelGGL(rb::newton_init_kernel, dim3(launch_grid(Bp * NP)), dim3(256), 0, st, a);
   Tune best;
-  best.lu_lds = c->lu_lds;
+  best.lu = c->lu;
   float best_ms = 1e30f;
   for (int ns : {2, 4, 8, 16, default_nsplit(Bp, N * N)}) {
     if (ns > rsplit || ns > a.nrb) continue;   // no slots / more splits than row blocks
@@ -679,15 +682,20 @@ int autotune_batch(rb_ctx* c, Set* s, int set, rb::NewtonF64Args a, const rb_sol
     }
   }
   if (!lp && NP <= 64) {
-    float lu_ms[2] = {0.f, 0.f};
-    for (int v = 0; v < 2; ++v) {
+    float lu_best = 1e30f;
+    for (int v : {RB_LU_READLANE, RB_LU_LDS, RB_LU_MFMA}) {
+      if (v == RB_LU_MFMA && N > RB_LU_MFMA_MAX_N) continue;
       hipLaunchKernelGGL(rb::newton_init_kernel, dim3(launch_grid(Bp * NP)), dim3(256), 0, st, a);
       if (int rc = contract(best.nsplit)) return release(rc);
-      if (int rc = timed([&] { return launch_rc(rb::launch::lu_f64(NP, a, 0, v == 1, st),
-                                                "autotune lu"); }, &lu_ms[v]))
+      float ms = 0.f;
+      if (int rc = timed([&] { return launch_rc(rb::launch::lu_f64(NP, a, 0, v, st),
+                                                "autotune lu"); }, &ms))
         return release(rc);
+      if (ms < lu_best) {
+        lu_best = ms;
+        best.lu = v;
+      }
     }
-    best.lu_lds = lu_ms[1] < lu_ms[0];
   }
   c->tune[std::make_tuple(set, N, o.precision, batch_class(Bp))] = best;
   *out = best;
@@ -771,7 +779,12 @@ int rb_create(int device, size_t hbm_budget_bytes, rb_ctx** out) {
   c->device = device;
   c->scratch = sp;
   c->budget = hbm_budget_bytes;
-  if (const char* v = getenv("RB_LU_BCAST")) c->lu_lds = (strcmp(v, "lds") == 0);
+  if (const char* v = getenv("RB_LU")) {
+    if (strcmp(v, "auto") == 0) c->lu = RB_LU_AUTO;
+    else if (strcmp(v, "readlane") == 0) c->lu = RB_LU_READLANE;
+    else if (strcmp(v, "lds") == 0) c->lu = RB_LU_LDS;
+    else if (strcmp(v, "mfma") == 0) c->lu = RB_LU_MFMA;
+  }
   if (const char* v = getenv("RB_AUTOTUNE")) c->autotune = (strcmp(v, "0") != 0);
   *out = c;
   g_err.clear();
@@ -997,7 +1010,7 @@ int rb_tuned_config(rb_ctx* c, int set, int N, int precision, int B, int* nsplit
   std::lock_guard<std::mutex> lk(c->mu);
   const Tune t = tune_for(c, set, N, precision, ceil_to(B < 1 ? 1 : B, rb::kTile));
   *nsplit = t.nsplit;
-  *lu_variant = t.lu_lds ? 1 : 0;
+  *lu_variant = t.lu;
   return RB_OK;
 }
 
@@ -1138,7 +1151,7 @@ int rb_solve_uneven(rb_ctx* c, int set, int B, const int* Nd, int ldu, const dou
     key.push_back(g.N);
     key.push_back(g.Bp);
     key.push_back(g.t.nsplit);
-    key.push_back(g.t.lu_lds);
+    key.push_back(g.t.lu);
   }
   auto run_group = [&](Group& g, hipStream_t gst) {
     return enqueue_solve(c, s, args_of(g, g.t.nsplit), o, g.t, base + g.region, gst);
@@ -1344,6 +1357,31 @@ int rb_recover_pressure_uneven(rb_ctx* c, int set, int B, const int* Nd, int Np,
   return RB_OK;
 }
 
+int rb_reconstruct_pressure(rb_ctx* c, int B, int N, int Np, const double* Pc, int ldpc,
+                            const double* u, int ldu, double* p, int ldp, void* stream) {
+  if (!c) return fail(RB_E_INVAL, "rb_reconstruct_pressure: NULL context");
+  if (B < 0 || N < 1 || N > RB_MAX_N || Np < 1 || Np > RB_MAX_NP)
+    return fail(RB_E_INVAL, "rb_reconstruct_pressure: B=%d N=%d Np=%d out of range", B, N, Np);
+  if (ldpc < N || ldu < N || ldp < Np)
+    return fail(RB_E_INVAL, "rb_reconstruct_pressure: ldpc=%d ldu=%d ldp=%d too small", ldpc,
+                ldu, ldp);
+  if (B == 0) return RB_OK;
+  if (!Pc || !u || !p) return fail(RB_E_INVAL, "rb_reconstruct_pressure: NULL array");
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (int rc = use_device(c)) return rc;
+  const size_t lds = (size_t)N * Np * sizeof(double);
+  if (lds > 64 * 1024)
+    HIP_TRY(hipFuncSetAttribute((const void*)rb::reconstruct_kernel,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  const int64_t total = (int64_t)B * ldp;
+  const int grid = (int)std::min<int64_t>(2048, (total + 255) / 256);
+  LaunchTimer t(c, FAM_RECONSTRUCT, (hipStream_t)stream);
+  hipLaunchKernelGGL(rb::reconstruct_kernel, dim3(grid), dim3(256), lds, (hipStream_t)stream, Pc,
+                     ldpc, N, Np, B, u, ldu, p, ldp);
+  HIP_TRY(hipGetLastError());
+  return RB_OK;
+}
+
 int rb_timing_enable(rb_ctx* c, int enable) {
   if (!c) return fail(RB_E_INVAL, "rb_timing_enable: NULL context");
   std::lock_guard<std::mutex> lk(c->mu);
@@ -1482,10 +1520,10 @@ int serve_group(int n, int Nm) { return (int)std::min<int64_t>(Nm, ceil_to(n, 16
 // default, whatever the batch size and whatever the tuning table holds. The partial sums of
 // A(mu) u (and of the pressure right-hand side) are then added in the same order for a
 // request alone and in any mix, so its result is the same bit for bit.
-Tune serve_tune(int N) {
+Tune serve_tune(int N, int lu) {
   Tune t;
   t.nsplit = default_nsplit(rb::kTile, N * N);
-  t.lu_lds = false;
+  t.lu = lu;
   return t;
 }
 int serve_press_nsplit(int N, int Np) { return default_nsplit(rb::kTile, Np * N); }
@@ -1497,7 +1535,7 @@ size_t batch_bytes(rb_server* v, const std::vector<std::pair<int, int>>& groups)
   for (auto& g : groups) {
     const int N = g.first, Np = v->s->Np;
     const int64_t Bp = ceil_to(g.second, rb::kTile);
-    b += solve_bytes(v->s, N, Bp, serve_tune(N).nsplit, v->o.precision);
+    b += solve_bytes(v->s, N, Bp, serve_tune(N, v->c->lu).nsplit, v->o.precision);
     if (v->o.pressure)
       b += (size_t)ceil_to((int64_t)pressure_bytes(g.second, N, Np, serve_press_nsplit(N, Np)),
                            256);
@@ -1562,7 +1600,7 @@ int launch_batch(rb_server* v, Lane& L) {
     const int64_t Bp = ceil_to(n, rb::kTile);
     Pack* pk;
     if (int rc = solve_pack_f64(c, s, N, &pk)) return rc;
-    const Tune t = serve_tune(N);
+    const Tune t = serve_tune(N, c->lu);
     rb::NewtonF64Args a =
         make_args(s, pk, N, n, Nm, o, ta + (int64_t)r0 * s->Q, tc + (int64_t)r0 * s->Qc,
                   tf + (int64_t)r0 * s->Qf, nullptr, nullptr, u + (int64_t)r0 * Nm, it + r0,

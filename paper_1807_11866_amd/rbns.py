@@ -20,7 +20,7 @@ RB_PREC_F64, RB_PREC_F32, RB_PREC_BF16, RB_PREC_BF16X3 = 0, 1, 2, 3
 
 EXPORTED = ("rb_create", "rb_destroy", "rb_last_error", "rb_hbm_used", "rb_load_tensors",
             "rb_theta", "rb_solve_batch", "rb_solve_batch_noalloc", "rb_solve_uneven", "rb_autotune", "rb_tuned_config",
-            "rb_recover_pressure", "rb_recover_pressure_uneven", "rb_server_start", "rb_server_submit", "rb_server_poll",
+            "rb_recover_pressure", "rb_recover_pressure_uneven", "rb_reconstruct_pressure", "rb_server_start", "rb_server_submit", "rb_server_poll",
             "rb_server_stats", "rb_server_stop", "rb_timing_enable", "rb_timing_read")
 RB_ST_FAILED = 5
 RB_MAX_N, RB_MAX_NP = 152, 64
@@ -107,6 +107,8 @@ def load(path=None):
     lib.rb_recover_pressure.argtypes = ([_vp] + [ct.c_int] * 6 + [_vp] * 7 + [_vp])
     lib.rb_recover_pressure_uneven.argtypes = ([_vp, ct.c_int, ct.c_int, _vp] + [ct.c_int] * 3 +
                                                [_vp] * 7 + [_vp])
+    lib.rb_reconstruct_pressure.argtypes = ([_vp, ct.c_int, ct.c_int, ct.c_int, _vp, ct.c_int,
+                                             _vp, ct.c_int, _vp, ct.c_int, _vp])
     lib.rb_server_start.argtypes = [_vp, ct.c_int, ct.POINTER(ServerOpts), ct.POINTER(_vp)]
     lib.rb_server_submit.argtypes = [_vp, ct.POINTER(Request), ct.c_int,
                                      ct.POINTER(ct.c_longlong)]
@@ -250,6 +252,12 @@ def rb_recover_pressure_uneven(ctx, set_id, B, N, Np, ldu, ldp, theta_a, theta_c
                                              _ptr(status), _stream(stream)))
 
 
+def rb_reconstruct_pressure(ctx, B, N, Np, Pc, ldpc, u, ldu, p, ldp, stream=None):
+    _check(load().rb_reconstruct_pressure(ctx, int(B), int(N), int(Np), _ptr(Pc), int(ldpc),
+                                          _ptr(u), int(ldu), _ptr(p), int(ldp),
+                                          _stream(stream)))
+
+
 def rb_timing_enable(ctx, enable=True):
     _check(load().rb_timing_enable(ctx, int(bool(enable))))
 
@@ -343,6 +351,18 @@ class Solver:
         rb_autotune(self.ctx, self.set, th["ta"].shape[0], N, th["ta"], th["tc"], th["tf"],
                     make_opts(tol, max_iter, precision, refine_steps), stream)
         return rb_tuned_config(self.ctx, self.set, N, precision, th["ta"].shape[0])
+
+    def reconstruct(self, Pc, u, N=None, out=None, stream=None):
+        """Pressure from a combined basis: p = Pc[:, :N] u (Pc a device [Np][>= N] array)."""
+        t = self.torch
+        N = self.N if N is None else N
+        Np = Pc.shape[0]
+        B = u.shape[0]
+        if out is None:
+            out = t.empty(B, Np, dtype=t.float64, device=self.dev)
+        rb_reconstruct_pressure(self.ctx, B, N, Np, Pc, Pc.shape[1], u, u.shape[1], out,
+                                out.shape[1], stream)
+        return out
 
     def pressure(self, th, u, N=None, Np=None, out=None, stream=None):
         t = self.torch

@@ -243,8 +243,17 @@ def assemble(N, Np, kmax, G, Q, Qc, Qf, Qb, seeds, force_kmax=4, forcing_scale=1
         Kdw = np.einsum("ab,nbcx->nacx", Km, dw)
         return (du.reshape(du.shape[0], -1) @ Kdw.reshape(dw.shape[0], -1).T) * w
 
-    A = np.stack([aform(dphi, dphi, Km).T for Km in Ks])          # A[q,i,j] = a(phi_j, phi_i)
-    Asv = np.stack([aform(dphi, ds, Km).T for Km in Ks])          # Asv[q,i,j] = a(phi_j, s_i)
+    if len(Ks) <= 12 and len(Ms) <= 4:
+        A = np.stack([aform(dphi, dphi, Km).T for Km in Ks])      # A[q,i,j] = a(phi_j, phi_i)
+        Asv = np.stack([aform(dphi, ds, Km).T for Km in Ks])      # Asv[q,i,j] = a(phi_j, s_i)
+    else:
+        # long expansions: every form is linear in its weight matrix, so the Q (Qc) operators
+        # are weighted sums of four base operators, one per weight entry
+        E2 = np.eye(4).reshape(4, 2, 2)
+        Ab = np.stack([aform(dphi, dphi, Eb).T for Eb in E2])
+        Asb = np.stack([aform(dphi, ds, Eb).T for Eb in E2])
+        A = np.einsum("qk,kij->qij", np.array(Ks).reshape(len(Ks), 4), Ab)
+        Asv = np.einsum("qk,kij->qij", np.array(Ks).reshape(len(Ks), 4), Asb)
 
     F = np.einsum("qbx,ibx->qi", g, phi) * w
     Fs = np.einsum("qbx,ibx->qi", g, s) * w
@@ -253,11 +262,14 @@ def assemble(N, Np, kmax, G, Q, Qc, Qf, Qb, seeds, force_kmax=4, forcing_scale=1
     Bp = np.stack([-np.einsum("ab,ibax,jx->ij", Bm, ds, p) * w for Bm in Bs])
 
     # c_q(u, v, t) = int ((u . grad) v) . (M_q t); tensors by chunks of the advecting index j.
-    Mphi = np.stack([np.einsum("bc,icx->ibx", Mm, phi) for Mm in Ms])      # (Qc, N, 2, X)
-    Ms_ = np.stack([np.einsum("bc,icx->ibx", Mm, s) for Mm in Ms])          # (Qc, Np, 2, X)
-    Ytest = np.concatenate([Mphi.reshape(Qc * N, 2 * X), Ms_.reshape(Qc * Np, 2 * X)])
-    C = np.empty((Qc, N, N, N))
-    Csv = np.empty((Qc, Np, N, N))
+    long_c = len(Ms) > 4 or len(Ks) > 12
+    Mw = np.eye(4).reshape(4, 2, 2) if long_c else Ms       # base weights for long expansions
+    Qw = len(Mw)
+    Mphi = np.stack([np.einsum("bc,icx->ibx", Mm, phi) for Mm in Mw])      # (Qw, N, 2, X)
+    Ms_ = np.stack([np.einsum("bc,icx->ibx", Mm, s) for Mm in Mw])          # (Qw, Np, 2, X)
+    Ytest = np.concatenate([Mphi.reshape(Qw * N, 2 * X), Ms_.reshape(Qw * Np, 2 * X)])
+    C = np.empty((Qw, N, N, N))
+    Csv = np.empty((Qw, Np, N, N))
     if jchunk is None:
         jchunk = max(1, min(N, int(2e8 // (N * 2 * X * 8))))
     for j0 in range(0, N, jchunk):
@@ -266,12 +278,85 @@ def assemble(N, Np, kmax, G, Q, Qc, Qf, Qb, seeds, force_kmax=4, forcing_scale=1
         T = np.einsum("jax,kabx->jkbx", phi[j0:j1], dphi)
         R = (Ytest @ T.reshape((j1 - j0) * N, 2 * X).T) * w             # (Qc(N+Np), (j,k))
         R = R.reshape(-1, j1 - j0, N)
-        C[:, :, j0:j1, :] = R[: Qc * N].reshape(Qc, N, j1 - j0, N)
-        Csv[:, :, j0:j1, :] = R[Qc * N:].reshape(Qc, Np, j1 - j0, N)
+        C[:, :, j0:j1, :] = R[: Qw * N].reshape(Qw, N, j1 - j0, N)
+        Csv[:, :, j0:j1, :] = R[Qw * N:].reshape(Qw, Np, j1 - j0, N)
+    if long_c:
+        Mk = np.array(Ms).reshape(len(Ms), 4)
+        C = np.einsum("qk,kijl->qijl", Mk, C)
+        Csv = np.einsum("qk,kijl->qijl", Mk, Csv)
 
     return dict(A=A, C=C, F=F, H=A[0].copy(), Bp=Bp, Asv=Asv, Csv=Csv, Fs=Fs,
                 Ks=np.array(Ks), Ms=np.array(Ms), Bs=np.array(Bs), K=K,
                 phi_c=phi_c, p_c=p_c, s_c=s_c, g_c=g_c)
+
+
+def assemble_coupled(N, Np, kmax, G, Q, Qc, Qf, seeds, force_kmax=4, forcing_scale=1.0):
+    """Operators of the coupled stabilised system (eqn block) as one velocity-only-shaped set.
+
+    The supremizer-enriched velocity space V = [phi_1..phi_N, s_1..s_Np] and the pressure space
+    give M = N + 2 Np unknowns x = (u, s, p). Written as A(mu) x + C(mu)(x, x) = f(mu):
+      A_q (q < Q)   [[a_q(V_j, V_i), 0], [0, 0]]       (the velocity block, N + Np square)
+      A_Q           [[0, B^T], [B, 0]] with B[i][j] = b(p_i, V_j), the pressure form with the
+                    identity weight (b(p, w) = -int p div w), so B_vp = 0 for the solenoidal
+                    phi and B_ps is the supremizer Gramian
+      C_q           c_q(V_j, V_k, V_i) on the velocity block, zero elsewhere
+      F_q           [(g_q, V_i); 0]
+      H             blockdiag(a_0(V_j, V_i), I): H^1 seminorm on the velocity, L2 on p
+    The bases, forms and forcing are those of ``assemble`` with the same seeds (nested: the
+    first N velocity and Np pressure functions are the leading ones of a larger set). With the
+    affine coefficients (theta^a, 1) the solution is (u, 0, p) with u the velocity-only
+    solution and p its recovered pressure (eqn piolablock with B_vp = 0, f_p = 0).
+    """
+    if G <= 3 * kmax:
+        raise ValueError(f"G={G} must exceed 3*kmax={3 * kmax} for exact quadrature")
+    K, phi_c, p_c, s_c = _basis_coefficients(N, Np, kmax, seeds)
+    Ks, Ms, _ = _form_matrices(Q, Qc, 1, seeds)
+    g_c = _forcing(Qf, K, force_kmax, forcing_scale, seeds)
+    E = grid_modes(K, G)
+    X = G * G
+    w = 1.0 / X
+    Nv = N + Np
+    M = Nv + Np
+    v_c = np.concatenate([phi_c, s_c], axis=0)                               # (Nv, 2, W, 2)
+    V = on_grid(v_c, E)                                                      # (Nv, 2, X)
+    dV = np.stack([on_grid(deriv(v_c, K, a), E) for a in range(2)], 1)       # (Nv, a, b, X)
+    pg = on_grid(p_c, E)                                                     # (Np, X)
+    g = on_grid(g_c, E)
+
+    def aform(du, dw, Km):
+        Kdw = np.einsum("ab,nbcx->nacx", Km, dw)
+        return (du.reshape(du.shape[0], -1) @ Kdw.reshape(dw.shape[0], -1).T) * w
+
+    A = np.zeros((Q + 1, M, M))
+    for q, Km in enumerate(Ks):
+        A[q, :Nv, :Nv] = aform(dV, dV, Km).T                   # A[q,i,j] = a(V_j, V_i)
+    divV = dV[:, 0, 0] + dV[:, 1, 1]                           # (Nv, X)
+    Bm = -(pg @ divV.T) * w                                    # Bm[i, j] = b(p_i, V_j)
+    A[Q, Nv:, :Nv] = Bm
+    A[Q, :Nv, Nv:] = Bm.T
+    C = np.zeros((Qc, M, M, M))
+    MV = np.stack([np.einsum("bc,icx->ibx", Mm, V) for Mm in Ms])          # (Qc, Nv, 2, X)
+    T = np.einsum("jax,kabx->jkbx", V, dV)                                 # (Nv, Nv, 2, X)
+    R = (MV.reshape(Qc * Nv, 2 * X) @ T.reshape(Nv * Nv, 2 * X).T) * w
+    C[:, :Nv, :Nv, :Nv] = R.reshape(Qc, Nv, Nv, Nv)
+    F = np.zeros((Qf, M))
+    F[:, :Nv] = np.einsum("qbx,ibx->qi", g, V) * w
+    H = np.eye(M)
+    H[:Nv, :Nv] = A[0, :Nv, :Nv]
+    return dict(A=A, C=C, F=F, H=H, Nv=Nv, M=M)
+
+
+def make_coupled_set(cfg, N, Np):
+    """The coupled system of ``assemble_coupled`` for a configuration's bases and forms, as a
+    TensorSet of size N + 2 Np with Q + 1 affine terms (no pressure data: p is an unknown)."""
+    d = assemble_coupled(N, Np, cfg["kmax"], cfg["G_quad"], cfg["Q"], cfg["Qc"], cfg["Qf"],
+                         cfg["seeds"], cfg.get("force_kmax", 4), cfg.get("forcing_scale", 1.0))
+    M = d["M"]
+    return TensorSet(N=M, Q=cfg["Q"] + 1, Qc=cfg["Qc"], Qf=cfg["Qf"], Np=0, Qb=1, A=d["A"],
+                     C=d["C"], F=d["F"], H=d["H"], Bp=np.zeros((1, 0, 0)),
+                     Asv=np.zeros((cfg["Q"] + 1, 0, M)), Csv=np.zeros((cfg["Qc"], 0, M, M)),
+                     Fs=np.zeros((cfg["Qf"], 0)),
+                     meta=dict(coupled=True, Nvel=N, Npres=Np, Nsup=Np))
 
 
 _CACHE_KEYS = ("N", "Np", "kmax", "G_quad", "Q", "Qc", "Qf", "Qb", "force_kmax",
@@ -326,6 +411,18 @@ def draw_mu(cfg, B=None, seed_offset=0):
     mu[:, 0] = np.deg2rad(lo + (hi - lo) * u[:, 0])
     mu[:, 1] = rlo + (rhi - rlo) * u[:, 1]
     return mu
+
+
+def gauss_grid_mu(cfg, n=15):
+    """n x n Gauss-Legendre points over the configuration's (alpha, Re) box, alpha in rad (a
+    training ensemble of the shape the paper uses: 15 x 15 Gauss points of its parameters)."""
+    x, _ = np.polynomial.legendre.leggauss(n)
+    lo, hi = np.deg2rad(cfg["alpha_deg"][0]), np.deg2rad(cfg["alpha_deg"][1])
+    rlo, rhi = cfg["Re"]
+    a = lo + (hi - lo) * (x + 1.0) / 2.0
+    r = rlo + (rhi - rlo) * (x + 1.0) / 2.0
+    A, Rr = np.meshgrid(a, r, indexing="ij")
+    return np.column_stack([A.ravel(), Rr.ravel()])
 
 
 def draw_basis_sizes(cfg, B=None, seed_offset=0):
