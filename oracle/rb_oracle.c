@@ -52,6 +52,9 @@ typedef struct {
 
 enum { ORC_OK = 0, ORC_MAXIT = 1, ORC_SINGULAR = 2, ORC_NONFINITE = 3, ORC_BADN = 4 };
 
+#define ORC_MAX_Q  64                /* affine terms of a; 4n + 2 = 50 at the paper's n = 12  */
+#define ORC_MAX_QC 64                /* affine terms of c                                      */
+
 /* ---------------------------------------------------------------------------------------
  * Parameter functions theta(mu), mu = (alpha [rad], Re). The paper's own coefficients are
  * powers of the rotation angle and the viscosity (Section 5); these families keep that shape:
@@ -65,7 +68,9 @@ int orc_theta(int Q, int Qc, int Qf, int Qb, double alpha, double Re,
     double la[12];
     double lc[4];
     int q;
-    if (Q < 1 || Q > 12 || Qc < 1 || Qc > 4 || Qf < 1 || Qf > 2 || Qb < 1 || Qb > 2) return -1;
+    if (Q < 1 || Q > ORC_MAX_Q || Qc < 1 || Qc > ORC_MAX_QC || Qf < 1 || Qf > 2 || Qb < 1 ||
+        Qb > 2)
+        return -1;
     la[0] = 1.0 / Re;
     la[1] = cos(a);
     la[2] = sin(a);
@@ -82,8 +87,21 @@ int orc_theta(int Q, int Qc, int Qf, int Qb, double alpha, double Re,
     lc[1] = cos(a);
     lc[2] = sin(a);
     lc[3] = a;
-    for (q = 0; q < Q; ++q) ta[q] = la[q];
-    for (q = 0; q < Qc; ++q) tc[q] = lc[q];
+    /* Longer expansions are those of the Piola-mapped forms (Section 5): truncated power
+     * series in the angle, every viscous term carrying 1/Re, theta^a_q = a^q / Re and
+     * theta^c_q = a^q (q = 0, 1, ...). */
+    if (Q <= 12) {
+        for (q = 0; q < Q; ++q) ta[q] = la[q];
+    } else {
+        double pw = 1.0 / Re;
+        for (q = 0; q < Q; ++q) { ta[q] = pw; pw *= a; }
+    }
+    if (Qc <= 4) {
+        for (q = 0; q < Qc; ++q) tc[q] = lc[q];
+    } else {
+        double pw = 1.0;
+        for (q = 0; q < Qc; ++q) { tc[q] = pw; pw *= a; }
+    }
     if (tf) {
         if (Qf == 1) tf[0] = 1.0;
         else { tf[0] = cos(a); tf[1] = sin(a); }
@@ -360,7 +378,7 @@ int orc_solve_batch(const orc_set *S, int B, const int *Nreq, const double *mu,
     for (b = 0; b < B; ++b) {
         const int Nm = S->Nm;
         int n = Nreq ? Nreq[b] : Nm;
-        double ta[12], tc[4], tf[2], tb[2];
+        double ta[ORC_MAX_Q], tc[ORC_MAX_QC], tf[2], tb[2];
         double *f = (double *)malloc(sizeof(double) * Nm);
         double *ub = u + (size_t)b * Nm;
         int q, i;

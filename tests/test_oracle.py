@@ -69,7 +69,24 @@ def test_theta_special_values(O):
     assert abs(ta[3] ** 2 - ta[4]) < 1e-15 and abs(ta[3] * ta[4] - ta[5]) < 1e-15
     assert np.array_equal(O.theta(3, 1, 1, 1, a, 100.0)[2], [1.0])
     with pytest.raises(ValueError):
-        O.theta(13, 1, 1, 1, a, 100.0)
+        O.theta(65, 1, 1, 1, a, 100.0)
+
+
+def test_theta_piola_power_families(O):
+    """Expansions longer than the trigonometric lists are the Piola-mapped forms' power series
+    in the angle (Section 5; 4n + 2 = 50 terms of a and 4n + 1 = 49 of c at n = 12): checked
+    against closed forms of the truncated geometric series and of the limits."""
+    re = 640.0
+    ta, tc, _, _ = O.theta(50, 49, 2, 2, 0.0, re)
+    assert ta[0] == 1.0 / re and np.all(ta[1:] == 0.0)          # alpha = 0: only the constant
+    assert tc[0] == 1.0 and np.all(tc[1:] == 0.0)
+    a = np.deg2rad(35.0)
+    ta, tc, _, _ = O.theta(50, 49, 2, 2, a, re)
+    assert abs(ta.sum() * re - (1 - a ** 50) / (1 - a)) < 1e-14 * (1 - a) ** -1
+    assert abs(tc.sum() - (1 - a ** 49) / (1 - a)) < 1e-14 * (1 - a) ** -1
+    assert np.allclose(ta[1:] / ta[:-1], a, rtol=1e-15) and np.allclose(tc[1:] / tc[:-1], a, rtol=1e-15)
+    # a short family keeps the trigonometric list
+    assert np.array_equal(O.theta(12, 4, 2, 2, a, re)[0][:3], O.theta(3, 1, 2, 2, a, re)[0])
 
 
 # ----------------------------------------------------------------- GEPP ----
