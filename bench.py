@@ -365,6 +365,8 @@ def main():
     ap.add_argument("--coupled", type=int, default=1,
                     help="time the coupled stabilised (naive) solver against the block method "
                          "at m = 10, 20, 30 (0 = skip)")
+    ap.add_argument("--assemble", type=int, default=1,
+                    help="time the offline convection-tensor assembly on the GPU (0 = skip)")
     ap.add_argument("--reconstruct", type=int, default=1,
                     help="time the combined-basis pressure reconstruction (0 = skip)")
     ap.add_argument("--autotune", action="store_true",
@@ -380,9 +382,15 @@ def main():
             " DESIGN.md describes how the path would shard)")
         sys.exit(2)
 
-    if args.workload != "batched_n50":
+    if not args.workload.startswith("batched_"):
         other_workload(args)
         return
+    if args.workload != "batched_n50":
+        # another batched tensor set (batched_n50_q50: the paper-shaped term counts): the
+        # batched FP64 step and its roofline only
+        args.plain, args.coupled, args.reconstruct, args.mixed_refine = 0, 0, 0, -1
+        args.assemble = 0
+        args.serve_rates = ""
 
     import torch
     from paper_1807_11866_amd import rbns
@@ -591,6 +599,35 @@ def main():
             sc.close()
         extra["coupled_vs_block"] = cres
 
+    # ---- offline: the convection tensors by quadrature on the GPU (eqn tensor) -------------
+    if args.assemble:
+        from rbinputs.synth import quadrature_fields
+        fq = quadrature_fields(N, Np, cfg["kmax"], cfg["G_quad"], ts.Q, ts.Qc, ts.Qb,
+                               cfg["seeds"])
+        Xq = fq["phi"].shape[-1]
+        phiT = torch.as_tensor(np.ascontiguousarray(fq["phi"].transpose(2, 1, 0)), device=dev)
+        dphiT = torch.as_tensor(np.ascontiguousarray(fq["dphi"].transpose(3, 1, 2, 0)), device=dev)
+        cout = torch.empty(ts.Qc, N, N, N, **f64)
+        rbns.rb_assemble_convection(s.ctx, N, N, Xq, ts.Qc, phiT, dphiT, phiT, fq["M"],
+                                    fq["w"], cout, stream)           # warm (workspace)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        nas = 5
+        ev0.record(stream)
+        for _ in range(nas):
+            rbns.rb_assemble_convection(s.ctx, N, N, Xq, ts.Qc, phiT, dphiT, phiT, fq["M"],
+                                        fq["w"], cout, stream)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ams = ev0.elapsed_time(ev1) / nas
+        aflop = 8.0 * N * Xq * N * N + 8.0 * Xq * N * N        # four base contractions + D_b
+        dif = float(np.abs(cout.cpu().numpy() - ts.C).max() / np.abs(ts.C).max())
+        extra["assembly"] = dict(ms=ams, tensor=f"C [{ts.Qc}][{N}][{N}][{N}] from {Xq} points",
+                                 achieved_tflops=aflop / (ams * 1e-3) / 1e12,
+                                 frac_fp64_mfma=aflop / (ams * 1e-3) / 1e12 / PEAK["fp64_mfma_tflops"],
+                                 max_rel_diff_vs_generator=dif)
+        log(f"[bench] tensor assembly: {ams:.3f} ms, {extra['assembly']['achieved_tflops']:.1f} "
+            f"TFLOP/s, max rel. difference {dif:.1e}")
+
     # ---- plain per-solve GPU path: the same library, one request per call ------------------
     if args.plain > 0:
         P = min(args.plain, B)
@@ -726,7 +763,8 @@ def main():
         cpu = cpu_baseline(ts, mu_h, cfg, args)
 
     res = {
-        "metric": "reduced NS solves/sec at N=50 (batched, velocity Newton + pressure recovery)",
+        "metric": (f"reduced NS solves/sec at N={N} (batched, velocity Newton + pressure "
+                   f"recovery{', Q=%d, Qc=%d' % (ts.Q, ts.Qc) if args.workload != 'batched_n50' else ''})"),
         "value": value,
         "unit": "solves/s",
         "n_gpus": 1,

@@ -47,6 +47,11 @@ extern "C" {
 #define RB_ST_SINGULAR   2    /* zero pivot in the Newton (or pressure) system               */
 #define RB_ST_NONFINITE  3    /* NaN or Inf in an operand, update or iterate                 */
 #define RB_ST_BADN       4    /* basis size out of range for the loaded set                  */
+#define RB_ST_REFINED    6    /* mixed precisions: the refinement steps ran out while every
+                                 refinement update after the first was at most half the one
+                                 before it: the error is of the order of the last update times
+                                 that contraction; a refinement that stagnates or grows ends
+                                 RB_ST_MAXIT instead                                          */
 
 /* arithmetic of the Newton iteration */
 #define RB_PREC_F64      0    /* FP64 tensors, FP64 MFMA contraction, FP64 LU                */
@@ -99,8 +104,9 @@ typedef struct {
 #define RB_MAX_N      152   /* basis size, mixed precisions (FP32 LU)                   */
 #define RB_MAX_N_F64   96   /* basis size, RB_PREC_F64 (FP64 LU rows in registers)      */
 #define RB_MAX_NP      64   /* pressure basis size                                      */
-#define RB_MAX_Q   12
-#define RB_MAX_QC   4
+#define RB_MAX_Q   64   /* affine terms of a (the paper's Piola expansion: 4n + 2 = 50)  */
+#define RB_MAX_QC  64   /* affine terms of c (4n + 1 = 49); mixed precisions: Q <= 12,
+                           Qc <= 4                                                       */
 #define RB_MAX_QF   2
 #define RB_MAX_QB   2
 
@@ -136,8 +142,12 @@ const char *rb_last_error(void);
 size_t rb_hbm_used(const rb_ctx *ctx);
 
 /*
- * rb_load_tensors: copy a model's reduced operators to the device (FP64, plus the packed
- * contraction operands built from them) and return its set id. The caller may free the host
+ * rb_load_tensors: copy a model's reduced operators (the affine matrices of Section 3.4, the
+ * third-order convection tensors of eqn tensor in Section 3.5, and the supremizer-tested
+ * pressure operators of Section 4.1) to the device (FP64, plus the packed contraction
+ * operands built from them) and return its set id. Low-precision copies (FP32, BF16) are
+ * built from the FP64 tensors on the device the first time a precision is used, so the
+ * descriptor carries no storage type. The caller may free the host
  * arrays on return. Synchronous.
  * Errors: RB_E_INVAL (NULL pointer, sizes out of range), RB_E_NOMEM (over budget),
  * RB_E_DEVICE.
@@ -145,12 +155,15 @@ size_t rb_hbm_used(const rb_ctx *ctx);
 int rb_load_tensors(rb_ctx *ctx, const rb_tensors_desc *desc, int *set_id_out);
 
 /*
- * rb_theta: evaluate the parameter functions of the loaded model's affine expansion for B
+ * rb_theta: evaluate the parameter functions of the loaded model's affine expansion (eqns
+ * split-a .. split-d1 of Section 2.4; the functions are a reading, see below) for B
  * parameters mu[b] = (alpha [rad], Re) (device, [B][2]). Writes theta_a [B][Q],
  * theta_c [B][Qc], theta_f [B][Qf] and, if the set has pressure data and theta_b != NULL,
  * theta_b [B][Qb] (all device). Families (trigonometric / polynomial in alpha, viscous 1/Re):
  *   theta_a = first Q of (1/Re, cos a, sin a, a, a^2, a^3, cos 2a, sin 2a, 1 - cos a, a^4,
  *             a cos a, a sin a);  theta_c = first Qc of (1, cos a, sin a, a);
+ *   longer expansions (Q > 12, Qc > 4) are the Piola-mapped forms' truncated power series in
+ *   the angle (Section 5): theta_a[q] = a^q / Re, theta_c[q] = a^q;
  *   theta_f = (1) if Qf = 1, else (cos a, sin a);  theta_b = (1) if Qb = 1, else (1, a).
  * Errors: RB_E_INVAL.
  */
@@ -158,8 +171,9 @@ int rb_theta(rb_ctx *ctx, int set, int B, const double *mu, double *theta_a, dou
              double *theta_f, double *theta_b, void *hip_stream);
 
 /*
- * rb_solve_batch: B independent reduced Newton solves at one basis size N (1 <= N <= the
- * set's N). Device inputs: theta_a [B][Q], theta_c [B][Qc], and either theta_f [B][Qf] or
+ * rb_solve_batch: B independent reduced Newton solves of the velocity-only system (eqn
+ * velonly, Section 2.2), the Jacobian assembled from the tensors (Section 3.5), at one basis
+ * size N (1 <= N <= the set's N; per-request sizes: rb_solve_uneven). Device inputs: theta_a [B][Q], theta_c [B][Qc], and either theta_f [B][Qf] or
  * f_override [B][ldu] (right-hand sides replacing f(mu), e.g. for manufactured solutions);
  * u0 [B][ldu] initial iterates or NULL (zero: the first step is then the Stokes solve).
  * Device outputs: u [B][ldu] (entries >= N are set to 0), iters [B] (Newton updates applied),
@@ -168,9 +182,11 @@ int rb_theta(rb_ctx *ctx, int set, int B, const double *mu, double *theta_a, dou
  * Mixed precisions (RB_PREC_F32 / RB_PREC_BF16 / RB_PREC_BF16X3): the low-precision phase stops
  * a request when its update is below tol or has stagnated (update <= 5e-2 ||u|| for BF16,
  * 1e-3 ||u|| for the others, and no longer halving), or at max_iter. RB_PREC_BF16X3 needs
- * Qc*N <= 640, RB_PREC_BF16 likewise. Then every request without a failure status takes
+ * Qc*N <= 640, RB_PREC_BF16 likewise; the mixed precisions need Q <= 12 and Qc <= 4
+ * (RB_E_UNSUPPORTED otherwise: long expansions run in FP64). Then every request without a failure status takes
  * up to refine_steps refinement steps (FP64 residual, the Jacobian of its last low-precision
- * step) until an update is below tol (status RB_ST_CONVERGED, else RB_ST_MAXIT). iters
+ * step) until an update is below tol (status RB_ST_CONVERGED, else RB_ST_REFINED or
+ * RB_ST_MAXIT, see RB_ST_REFINED). iters
  * counts both kinds of updates.
  * Errors: RB_E_INVAL (NULL, B < 0, N or ldu out of range, bad opts), RB_E_NOMEM,
  * RB_E_UNSUPPORTED (RB_PREC_F64 with N > RB_MAX_N_F64), RB_E_DEVICE. B == 0 is a no-op.
@@ -289,6 +305,25 @@ int rb_recover_pressure(rb_ctx *ctx, int set, int B, int N, int Np, int ldu, int
  */
 int rb_reconstruct_pressure(rb_ctx *ctx, int B, int N, int Np, const double *Pc, int ldpc,
                             const double *u, int ldu, double *p, int ldp, void *hip_stream);
+
+/*
+ * rb_assemble_convection: offline assembly of the convection tensors by quadrature on the
+ * device (eqn tensor, Section 3.5; the offline step, not the online solve): for the affine
+ * terms c_q(u, v, t) = int ((u . grad) v) . (M_q t),
+ *   out[q][i][j][k] = w * sum_x sum_{b,c} M_q[b][c] ((phi_j . grad) phi_k)^b(x) t_i^c(x),
+ * i < R (test functions), j, k < N (velocity functions), x < X (quadrature points, weight w).
+ * With t = phi this is C_q[i][j][k] of rb_tensors_desc; with t = the supremizers, C_sv.
+ * The Qc tensors are formed from four base contractions (R x X x N^2 each) on MFMA-F64.
+ * Device inputs, point-major: phiT [X][2][N] (phi_j^a(x) at (x*2 + a)*N + j), dphiT
+ * [X][2][2][N] (d_a phi_k^b(x) at ((x*2 + a)*2 + b)*N + k), testT [X][2][R]. Host input:
+ * M [Qc][2][2]. Device output: out [Qc][R][N][N]. Synchronous (returns when out is written);
+ * uses the stream's workspace (8 * 4 * R * N^2 bytes per quadrature split, at most 16).
+ * Errors: RB_E_INVAL (NULL, N or R outside [1, RB_MAX_N], Qc outside [1, RB_MAX_QC],
+ * X < 1), RB_E_NOMEM, RB_E_DEVICE.
+ */
+int rb_assemble_convection(rb_ctx *ctx, int N, int R, int X, int Qc, const double *phiT,
+                           const double *dphiT, const double *testT, const double *M, double w,
+                           double *out, void *hip_stream);
 
 /* ------------------------------------------------------------------ serving --------- */
 /*

@@ -24,6 +24,8 @@ namespace rb {
 
 constexpr int kWaves = 4;      // wavefronts per workgroup
 constexpr int kThreads = kWave * kWaves;
+// Lengths of the trigonometric theta lists (longer expansions take the power families; the
+// low-precision contraction holds these many theta values per request in registers).
 constexpr int kMaxQ = 12, kMaxQc = 4, kMaxQf = 2, kMaxQb = 2;
 
 // ------------------------------------------------------------------ packing -----------
@@ -74,8 +76,18 @@ static __global__ void theta_kernel(const double* __restrict__ mu, int B, int Q,
   const double la[kMaxQ] = {1.0 / re, ca, sa, a, a * a, a * a * a, cos(2.0 * a),
                             sin(2.0 * a), 2.0 * h * h, a * a * a * a, a * ca, a * sa};
   const double lc[kMaxQc] = {1.0, ca, sa, a};
-  for (int q = 0; q < Q; ++q) ta[(int64_t)b * Q + q] = la[q];
-  for (int q = 0; q < Qc; ++q) tc[(int64_t)b * Qc + q] = lc[q];
+  // Longer expansions are the Piola-mapped forms' truncated power series in the angle
+  // (Section 5): theta^a_q = a^q / Re (viscous), theta^c_q = a^q.
+  double pw = 1.0 / re;
+  for (int q = 0; q < Q; ++q) {
+    ta[(int64_t)b * Q + q] = Q <= kMaxQ ? la[q] : pw;
+    pw *= a;
+  }
+  pw = 1.0;
+  for (int q = 0; q < Qc; ++q) {
+    tc[(int64_t)b * Qc + q] = Qc <= kMaxQc ? lc[q] : pw;
+    pw *= a;
+  }
   if (tf) {
     if (Qf == 1) tf[b] = 1.0;
     else { tf[2 * (int64_t)b] = ca; tf[2 * (int64_t)b + 1] = sa; }
@@ -111,6 +123,7 @@ struct NewtonF64Args {
   const double* op;        // packed solve operand
   int nrb, nks_s, nks;     // row blocks, affine k-steps, total k-steps
   int nchunk;              // tensor chunks
+  int naff;                // affine chunks (long expansions; 0: affine part of kAmax k-steps)
   int N, Nm, Q, Qc, Qf, B, ldu, maxit;
   double tol;
   const double* ta;        // [B][Q]
@@ -172,7 +185,10 @@ static __global__ void newton_init_kernel(NewtonF64Args a) {
 // pipeline does not drain between groups. The affine part is padded to kAmax = 3 k-steps
 // (zero columns) so that every row block has the same static pipeline. Tensor parts longer
 // than 64 k-steps run as nchunk chunks, each walking the row blocks again with fresh
-// accumulators (the Jacobian adds each later chunk to what the earlier ones stored).
+// accumulators (the Jacobian adds each later chunk to what the earlier ones stored). Long
+// affine expansions (Q > 12, the Piola-mapped forms of Section 5) go in naff chunks of their
+// own in front of the tensor chunks, with the same chunk length, and the affine accumulator
+// is folded at the end of those passes.
 //
 // Rows are m = j*R + i (R = N for the solve operand, R = Np for the pressure one). The
 // epilogue folds acc[m, b] * u_j(b) into per-row sums p_i(b) in LDS:
@@ -193,9 +209,12 @@ constexpr int kMaxKC = 40;     // longest tensor chunk held in registers (no spi
 constexpr int kAmax = 3;       // affine k-steps of every packed row block (Q <= 12)
 
 struct ContractArgs {
-  const double* op;        // packed operand [nrb][nks][64], nks = kAmax + nchunk*KC
-  int nrb, nks, kA;        // row blocks, k-steps per row block, affine k-steps (= kAmax)
+  const double* op;        // packed operand [nrb][nks][64], nks = kA + nchunk*KC
+  int nrb, nks, kA;        // row blocks, k-steps per row block, affine k-steps (kAmax, or
+                           // naff*KC for long expansions)
   int nchunk;              // tensor chunks of KC k-steps
+  int naff;                // affine chunks of KC k-steps (0: the kAmax affine k-steps ride
+                           // in front of the first tensor chunk)
   int nsplit;              // row splits per tile (1..kMaxSplit)
   int R, N, M;             // rows m = j*R + i, M = R*N
   int Q, Qc, B;
@@ -212,11 +231,11 @@ struct ContractArgs {
   int ldp;
 };
 
-// LDS: the tile's iterates [kTile][N], row sums [kTile][R], theta^c [kTile][kMaxQc] and, for
-// the Jacobian, the transpose stage [kWaves][16][kStageLd].
+// LDS: the tile's iterates [kTile][N], row sums [kTile][R] and, for the Jacobian, the
+// transpose stage [kWaves][16][kStageLd].
 constexpr int kStageLd = 20;   // padded row of the stage (16-byte aligned, spreads banks)
 __host__ __device__ inline int64_t contract_lds_bytes(int N, int R, bool jac) {
-  return 8 * ((int64_t)kTile * (N + R + kMaxQc) + (jac ? kWaves * 16 * kStageLd : 0));
+  return 8 * ((int64_t)kTile * (N + R) + (jac ? kWaves * 16 * kStageLd : 0));
 }
 
 constexpr int kModeJac = 0, kModePressure = 1, kModeResid = 2;
@@ -228,7 +247,6 @@ void contract_f64_kernel(ContractArgs a) {
   const int N = a.N, R = a.R;
   double* ul = smem;                       // [kTile][N]
   double* pl = ul + kTile * N;             // [kTile][R]
-  double* tcl = pl + kTile * R;            // [kTile][kMaxQc]
 
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int split = blockIdx.x % a.nsplit;
@@ -240,10 +258,6 @@ void contract_f64_kernel(ContractArgs a) {
     ul[idx] = bg < a.B ? a.U[(int64_t)bg * a.ldU + l] : 0.0;
   }
   for (int idx = tid; idx < kTile * R; idx += kThreads) pl[idx] = 0.0;
-  for (int idx = tid; idx < kTile * kMaxQc; idx += kThreads) {
-    const int b = idx / kMaxQc, q = idx - b * kMaxQc, bg = b0 + b;
-    tcl[idx] = (bg < a.B && q < a.Qc) ? a.tc[(int64_t)bg * a.Qc + q] : 0.0;
-  }
 
   // This lane's B-operand column: request bl = 16*wv + lane%16, k = ks*4 + lane/16.
   // Affine rows k < 4*kAmax: theta^a_k (0 beyond Q); tensor row t = q*N + l: theta^c_q u_l.
@@ -261,7 +275,7 @@ void contract_f64_kernel(ContractArgs a) {
   const int rb_lo = (int)((int64_t)split * a.nrb / a.nsplit);
   const int rb_hi = (int)((int64_t)(split + 1) * a.nrb / a.nsplit);
   const int col = bl;                      // accumulator column (request) of this lane
-  double* stg = tcl + kTile * kMaxQc + wv * 16 * kStageLd;   // this wavefront's stage
+  double* stg = pl + kTile * R + wv * 16 * kStageLd;   // this wavefront's stage
 
   // Accumulator layout of v_mfma_f64_16x16x4f64: lane l, element v = row l/16 + 4v,
   // column l%16 of the 16x16 tile. fold(): wt * acc[m] * u_j into p_i for m = j*R + i.
@@ -282,8 +296,10 @@ void contract_f64_kernel(ContractArgs a) {
   };
 
   // One pass over this split's row blocks for the k-steps [k_first, k_first + NKS) of every
-  // packed row block, with W values w[0..NKS).
-  auto pass = [&](auto nks_c, const double* w, int k_first, int chunk) {
+  // packed row block, with W values w[0..NKS). end_wt: weight of the accumulator folded into
+  // the row sums at the end of each row block (the Jacobian folds only the affine chunks of a
+  // long expansion, and writes its slice of J either way).
+  auto pass = [&](auto nks_c, const double* w, int k_first, int chunk, double end_wt) {
     constexpr int NKS = decltype(nks_c)::value;
     constexpr bool kAff = NKS == kAmax + KC;   // this pass starts with the affine k-steps
     if (rb_lo >= rb_hi) return;            // no row blocks in this split: load nothing
@@ -328,6 +344,7 @@ void contract_f64_kernel(ContractArgs a) {
 #pragma unroll
         for (int r = 0; r < kGroup; ++r) x[t][r] = x[NKS + t][r];
       if (kMode == kModeJac) {
+        if (end_wt != 0.0) fold(c, g0, end_wt);
         // stage [request][row] -> lane l takes request l/4, rows 4*(l%4)..+3 of the block
         const int q2 = lane >> 2, e0 = 4 * (lane & 3);
 #pragma unroll
@@ -345,33 +362,51 @@ void contract_f64_kernel(ContractArgs a) {
           }
         }
       } else {
-        fold(c, g0, kMode == kModeResid ? 0.5 : 1.0);
+        fold(c, g0, end_wt);
       }
     }
   };
 
   const double* ub = ul + bl * N;
-  const double* tcb = tcl + bl * kMaxQc;
-  for (int ch = 0; ch < a.nchunk; ++ch) {
+  // theta^c_q of this lane's request (read when q changes along the k range)
+  auto tcq = [&](int q) {
+    return (bg < a.B && q < a.Qc) ? a.tc[(int64_t)bg * a.Qc + q] : 0.0;
+  };
+  const double tens_wt = kMode == kModeJac ? 0.0 : (kMode == kModeResid ? 0.5 : 1.0);
+  for (int ch = 0; ch < a.naff + a.nchunk; ++ch) {
     double w[kAmax + KC];
-    {
-      int t = ch * KC * 4 + k0, q = 0;
-      while (t >= N && q < kMaxQc) { t -= N; ++q; }
-      if (q >= kMaxQc) t = 0;              // padding k-steps: W = 0, any valid index
+    if (ch < a.naff) {                     // affine chunk of a long expansion: W = theta^a
 #pragma unroll
       for (int ks = 0; ks < KC; ++ks) {
-        w[kAmax + ks] = (q < kMaxQc ? tcb[q < kMaxQc ? q : 0] : 0.0) * ub[t];
+        const int k = (ch * KC + ks) * 4 + k0;
+        w[kAmax + ks] = (bg < a.B && k < a.Q) ? a.ta[(int64_t)bg * a.Q + k] : 0.0;
+      }
+      pass(std::integral_constant<int, KC>{}, w + kAmax, ch * KC, ch, 1.0);
+      continue;
+    }
+    const int tch = ch - a.naff;            // tensor chunk: W = theta^c_q u_l, t = q*N + l
+    {
+      int t = tch * KC * 4 + k0, q = 0;
+      while (t >= N && q < a.Qc) { t -= N; ++q; }
+      double th = tcq(q);
+#pragma unroll
+      for (int ks = 0; ks < KC; ++ks) {
+        w[kAmax + ks] = q < a.Qc ? th * ub[t] : 0.0;   // padding k-steps: W = 0
         t += 4;
-        while (t >= N && q < kMaxQc) { t -= N; ++q; }
-        if (q >= kMaxQc) t = 0;
+        while (t >= N && q < a.Qc) {
+          t -= N;
+          ++q;
+          th = tcq(q);
+        }
+        if (q >= a.Qc) t = 0;
       }
     }
-    if (ch == 0) {
+    if (a.naff == 0 && ch == 0) {
 #pragma unroll
       for (int ks = 0; ks < kAmax; ++ks) w[ks] = wa[ks];
-      pass(std::integral_constant<int, kAmax + KC>{}, w, 0, 0);
+      pass(std::integral_constant<int, kAmax + KC>{}, w, 0, 0, tens_wt);
     } else {
-      pass(std::integral_constant<int, KC>{}, w + kAmax, kAmax + ch * KC, ch);
+      pass(std::integral_constant<int, KC>{}, w + kAmax, a.kA + tch * KC, ch, tens_wt);
     }
   }
   __syncthreads();

@@ -308,6 +308,12 @@ void contract_lp_kernel(ContractLpArgs a) {
   }
 }
 
+// Status of a request whose refinement steps ran out while each refinement update after the
+// first was at most half the update before it (the refinement still contracting): its error is
+// of the order of the last update times that contraction. RB_ST_MAXIT then marks stagnation or
+// divergence.
+constexpr int kStRefined = 6;
+
 struct LpNewtonArgs {
   int N, Nm, B;
   double tol;              // stopping test ||delta||_H <= tol ||u||_H
@@ -394,8 +400,10 @@ __global__ __launch_bounds__(kThreads) void lu_lp_kernel(LpNewtonArgs a, int it)
           a.s.done[b] = 1;
         } else if (!kRefine && it > 0 && nd <= a.stag * nu && nd > 0.5 * a.s.dprev[b]) {
           a.s.done[b] = 1;                 // stagnated: status stays RB_ST_MAXIT
+        } else if (kRefine) {              // still contracting: RB_ST_REFINED, else MAXIT
+          a.s.status[b] = nd <= 0.5 * a.s.dprev[b] ? kStRefined : 1;
         }
-        if (!kRefine) a.s.dprev[b] = nd;
+        a.s.dprev[b] = nd;
       }
     }
   }
@@ -447,18 +455,25 @@ __global__ __launch_bounds__(kWave * W) void lu_lp_mw_kernel(LpNewtonArgs a, int
     a.s.done[b] = 1;
   } else if (!refine && it > 0 && nd <= a.stag * nu && nd > 0.5 * a.s.dprev[b]) {
     a.s.done[b] = 1;
+  } else if (refine) {
+    a.s.status[b] = nd <= 0.5 * a.s.dprev[b] ? kStRefined : 1;
   }
-  if (!refine) a.s.dprev[b] = nd;
+  a.s.dprev[b] = nd;
 }
 
 // Between the phases: every request without a failure status is refined (status back to
-// RB_ST_MAXIT until a refinement update meets the tolerance).
-static __global__ void lp_refine_reset_kernel(int B, int64_t Bp, int* done, int* status) {
+// RB_ST_MAXIT until a refinement update meets the tolerance). The first refinement update has
+// nothing to contract against (the last low-precision updates are at the noise level of the
+// low precision, as large as the error the refinement removes); later ones are measured
+// against the one before.
+static __global__ void lp_refine_reset_kernel(int B, int64_t Bp, int* done, int* status,
+                                              double* dprev) {
   for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < Bp;
        b += (int64_t)gridDim.x * blockDim.x) {
     if (b >= B) { done[b] = 1; continue; }
     const int s = status[b];
     done[b] = s >= 2;
+    if (s < 2) dprev[b] = __builtin_huge_val();
     if (s < 2) status[b] = 1;
   }
 }

@@ -23,6 +23,7 @@
 #include "../../include/rbns.h"
 #include "rb_launch.hpp"
 #include "rb_reconstruct.hpp"
+#include "rb_assemble.hpp"
 
 // Device scratch of rb_solve_batch_noalloc: the Newton state of one call lives here instead of
 // in a per-stream workspace, so that entry point allocates nothing. Each device holds its own
@@ -64,6 +65,7 @@ struct Pack {              // packed MFMA operand for one basis size
   const void* lo = nullptr;  // BF16x3: low parts (inside buf)
   int nrb = 0, nks_s = 0, nks = 0;
   int nchunk = 1;          // tensor part = nchunk chunks of (nks - nks_s) / nchunk k-steps
+  int naff = 0;            // long expansions: affine chunks of the same length (nks_s of them)
 };
 
 struct Set {
@@ -179,7 +181,6 @@ int launch_grid(int64_t total) {
 // k-steps of a packed row block: affine part ceil(Q/4), tensor part ceil(Qc*N/4) split into
 // nchunk <= 64-k-step chunks of an even length KC (the FP64 contraction is instantiated per
 // even chunk length and holds one chunk of W in registers), zero padded.
-int affine_ksteps(int) { return rb::kAmax; }   // padded: one static pipeline for every Q
 void tensor_chunks(int Qc, int N, int* nchunk, int* kc) {
   const int raw = (int)(ceil_to((int64_t)Qc * N, 4) / 4);
   *nchunk = (raw + rb::kMaxKC - 1) / rb::kMaxKC;
@@ -191,11 +192,24 @@ int tensor_ksteps(int Qc, int N) {
   return n * kc;
 }
 
+// FP64 operand layout of basis size N: the affine part is padded to kAmax k-steps in front of
+// the first tensor chunk when Q <= 4*kAmax, else it takes naff chunks of its own (long
+// expansions); returns the affine k-steps.
+int f64_layout(const Set* s, int N, int* nchunk, int* kc, int* naff) {
+  tensor_chunks(s->Qc, N, nchunk, kc);
+  if (s->Q <= 4 * rb::kAmax) {
+    *naff = 0;
+    return rb::kAmax;
+  }
+  const int ka = (s->Q + 3) / 4;
+  *naff = (ka + *kc - 1) / *kc;
+  return *naff * *kc;
+}
+
 int make_pack(rb_ctx* c, Set* s, int N, int R, bool solve, Pack* p) {
   p->nrb = (int)(ceil_to((int64_t)N * R, 16) / 16);
-  p->nks_s = affine_ksteps(s->Q);
   int kc;
-  tensor_chunks(s->Qc, N, &p->nchunk, &kc);
+  p->nks_s = f64_layout(s, N, &p->nchunk, &kc, &p->naff);
   p->nks = p->nks_s + p->nchunk * kc;
   const int64_t total = (int64_t)p->nrb * p->nks * 64;
   int rc = dev_alloc(c, p->buf, total * sizeof(double));
@@ -337,9 +351,9 @@ size_t lp_extra_bytes(int64_t Bp, int NP, int64_t mp, int nsplit) {
 // (the mixed precisions keep their Jacobian in FP32 and need none).
 int jslices_for(const Set* s, int N, int precision) {
   if (precision != RB_PREC_F64) return 0;
-  int n, kc;
-  tensor_chunks(s->Qc, N, &n, &kc);
-  return n;
+  int n, kc, naff;
+  f64_layout(s, N, &n, &kc, &naff);
+  return naff + n;
 }
 
 // Register row length of the LU kernels (Newton and pressure): even up to 64 (one wavefront
@@ -401,7 +415,8 @@ int enqueue_newton(rb_ctx* c, const rb::NewtonF64Args& a, int lu, hipStream_t st
   const int64_t Bp = a.s.Bp;
   rb::ContractArgs g;
   g.op = a.op;
-  g.nrb = a.nrb; g.nks = a.nks; g.kA = a.nks_s; g.nchunk = a.nchunk; g.nsplit = a.s.nsplit;
+  g.nrb = a.nrb; g.nks = a.nks; g.kA = a.nks_s; g.nchunk = a.nchunk; g.naff = a.naff;
+  g.nsplit = a.s.nsplit;
   g.R = a.N; g.N = a.N; g.M = a.N * a.N;
   g.Q = a.Q; g.Qc = a.Qc; g.B = a.B; g.Bp = Bp;
   g.ta = a.ta; g.tc = a.tc;
@@ -454,6 +469,7 @@ int enqueue_newton_lp(rb_ctx* c, Set* s, const rb::NewtonF64Args& a, int prec, i
   rb::ContractArgs gr;                      // FP64 residual
   gr.op = (const double*)pf->buf.p;
   gr.nrb = pf->nrb; gr.nks = pf->nks; gr.kA = pf->nks_s; gr.nchunk = pf->nchunk;
+  gr.naff = pf->naff;
   gr.nsplit = nsplit;
   gr.R = N; gr.N = N; gr.M = N * N;
   gr.Q = a.Q; gr.Qc = a.Qc; gr.B = a.B; gr.Bp = Bp;
@@ -479,7 +495,7 @@ int enqueue_newton_lp(rb_ctx* c, Set* s, const rb::NewtonF64Args& a, int prec, i
   }
   if (refine > 0)
     hipLaunchKernelGGL(rb::lp_refine_reset_kernel, dim3(launch_grid(Bp)), dim3(256), 0, st,
-                       a.B, Bp, a.s.done, a.s.status);
+                       a.B, Bp, a.s.done, a.s.status, a.s.dprev);
   for (int r = 0; r < refine; ++r) {
     {
       LaunchTimer t(c, FAM_RESIDUAL, st);
@@ -522,6 +538,7 @@ int enqueue_pressure(rb_ctx* c, Set* s, int B, int N, int Np, int ldu, int ldp,
   rb::ContractArgs g;
   g.op = (const double*)pk->buf.p;
   g.nrb = pk->nrb; g.nks = pk->nks; g.kA = pk->nks_s; g.nchunk = pk->nchunk;
+  g.naff = pk->naff;
   g.R = Np; g.N = N; g.M = Np * N;
   g.Q = s->Q; g.Qc = s->Qc; g.B = B; g.Bp = Bp;
   g.ta = ta; g.tc = tc;
@@ -574,6 +591,15 @@ Tune tune_for(rb_ctx* c, int set, int N, int precision, int64_t Bp) {
   return t;
 }
 
+// The low-precision contraction keeps the trigonometric theta lists in registers: long
+// expansions run in FP64 only.
+int check_lp_terms(const char* fn, const Set* s, const rb_solve_opts& o) {
+  if (o.precision != RB_PREC_F64 && (s->Q > rb::kMaxQ || s->Qc > rb::kMaxQc))
+    return fail(RB_E_UNSUPPORTED, "%s: mixed precision takes Q <= %d and Qc <= %d (Q=%d Qc=%d)",
+                fn, rb::kMaxQ, rb::kMaxQc, s->Q, s->Qc);
+  return RB_OK;
+}
+
 int check_opts(const char* fn, const rb_solve_opts& o) {
   if (!(o.tol >= 0.0) || o.max_iter < 1 || o.max_iter > 1000)
     return fail(RB_E_INVAL, "%s: bad options (tol=%g, max_iter=%d)", fn, o.tol, o.max_iter);
@@ -594,6 +620,7 @@ rb::NewtonF64Args make_args(Set* s, Pack* pk, int N, int B, int ldu, const rb_so
   rb::NewtonF64Args a;
   a.op = (const double*)pk->buf.p;
   a.nrb = pk->nrb; a.nks_s = pk->nks_s; a.nks = pk->nks; a.nchunk = pk->nchunk;
+  a.naff = pk->naff;
   a.N = N; a.Nm = s->N; a.Q = s->Q; a.Qc = s->Qc; a.Qf = s->Qf; a.B = B; a.ldu = ldu;
   a.maxit = o.max_iter; a.tol = o.tol;
   a.ta = ta; a.tc = tc; a.tf = tf; a.fover = fover; a.u0 = u0; a.nreq = nreq;
@@ -640,7 +667,8 @@ int autotune_batch(rb_ctx* c, Set* s, int set, rb::NewtonF64Args a, const rb_sol
     if (!lp) {
       rb::ContractArgs g;
       g.op = a.op;
-      g.nrb = a.nrb; g.nks = a.nks; g.kA = a.nks_s; g.nchunk = a.nchunk; g.nsplit = nsplit;
+      g.nrb = a.nrb; g.nks = a.nks; g.kA = a.nks_s; g.nchunk = a.nchunk; g.naff = a.naff;
+      g.nsplit = nsplit;
       g.R = N; g.N = N; g.M = N * N;
       g.Q = a.Q; g.Qc = a.Qc; g.B = a.B; g.Bp = Bp;
       g.ta = a.ta; g.tc = a.tc; g.U = a.s.U; g.ldU = NP;
@@ -907,6 +935,7 @@ int rb_solve_batch(rb_ctx* c, int set, int B, int N, int ldu, const double* ta,
   rb_solve_opts o = {1e-12, 10, RB_PREC_F64, 1};
   if (opts) o = *opts;
   if (int rc = check_opts("rb_solve_batch", o)) return rc;
+  if (int rc = check_lp_terms("rb_solve_batch", s, o)) return rc;
   if (o.precision == RB_PREC_F64 && N > RB_MAX_N_F64)
     return fail(RB_E_UNSUPPORTED, "rb_solve_batch: FP64 solves take N <= %d (N=%d)",
                 RB_MAX_N_F64, N);
@@ -942,6 +971,7 @@ int rb_solve_batch_noalloc(rb_ctx* c, int set, int B, int N, int ldu, const doub
   rb_solve_opts o = {1e-12, 10, RB_PREC_F64, 1};
   if (opts) o = *opts;
   if (int rc = check_opts("rb_solve_batch_noalloc", o)) return rc;
+  if (int rc = check_lp_terms("rb_solve_batch_noalloc", s, o)) return rc;
   if (o.precision == RB_PREC_F64 && N > RB_MAX_N_F64)
     return fail(RB_E_UNSUPPORTED, "rb_solve_batch_noalloc: FP64 solves take N <= %d (N=%d)",
                 RB_MAX_N_F64, N);
@@ -986,6 +1016,7 @@ int rb_autotune(rb_ctx* c, int set, int B, int N, const double* ta, const double
   rb_solve_opts o = {1e-12, 10, RB_PREC_F64, 1};
   if (opts) o = *opts;
   if (int rc = check_opts("rb_autotune", o)) return rc;
+  if (int rc = check_lp_terms("rb_autotune", s, o)) return rc;
   if (o.precision == RB_PREC_F64 && N > RB_MAX_N_F64)
     return fail(RB_E_UNSUPPORTED, "rb_autotune: FP64 solves take N <= %d", RB_MAX_N_F64);
   if (!ta || !tc || !tf) return fail(RB_E_INVAL, "rb_autotune: NULL array");
@@ -1026,6 +1057,7 @@ int rb_solve_uneven(rb_ctx* c, int set, int B, const int* Nd, int ldu, const dou
   rb_solve_opts o = {1e-12, 10, RB_PREC_F64, 1};
   if (opts) o = *opts;
   if (int rc = check_opts("rb_solve_uneven", o)) return rc;
+  if (int rc = check_lp_terms("rb_solve_uneven", s, o)) return rc;
   if (B == 0) return RB_OK;
   if (!Nd || !ta || !tc || (!tf && !fover) || !u || !iters || !status)
     return fail(RB_E_INVAL, "rb_solve_uneven: NULL array");
@@ -1379,6 +1411,43 @@ int rb_reconstruct_pressure(rb_ctx* c, int B, int N, int Np, const double* Pc, i
   hipLaunchKernelGGL(rb::reconstruct_kernel, dim3(grid), dim3(256), lds, (hipStream_t)stream, Pc,
                      ldpc, N, Np, B, u, ldu, p, ldp);
   HIP_TRY(hipGetLastError());
+  return RB_OK;
+}
+
+int rb_assemble_convection(rb_ctx* c, int N, int R, int X, int Qc, const double* phiT,
+                           const double* dphiT, const double* testT, const double* M, double w,
+                           double* out, void* stream) {
+  if (!c) return fail(RB_E_INVAL, "rb_assemble_convection: NULL context");
+  if (N < 1 || N > RB_MAX_N || R < 1 || R > RB_MAX_N || X < 1 || Qc < 1 || Qc > RB_MAX_QC)
+    return fail(RB_E_INVAL, "rb_assemble_convection: N=%d R=%d X=%d Qc=%d out of range", N, R,
+                X, Qc);
+  if (!phiT || !dphiT || !testT || !M || !out)
+    return fail(RB_E_INVAL, "rb_assemble_convection: NULL array");
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (int rc = use_device(c)) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t wgs = (int64_t)((R + 63) / 64) * ((N + rb::kAsmWaves - 1) / rb::kAsmWaves) *
+                      ((N + 15) / 16);
+  // split the quadrature points until about 4096 wavefronts run (at most 16 splits, and at
+  // least 64 points per split)
+  int nsx = (int)std::min<int64_t>(16, std::max<int64_t>(1, (4096 + 4 * wgs - 1) / (4 * wgs)));
+  nsx = std::max(1, std::min(nsx, X / 64));
+  const size_t part_bytes = (size_t)nsx * 4 * R * N * N * sizeof(double);
+  Workspace* ws;
+  if (int rc = workspace(c, stream, part_bytes + 4 * Qc * sizeof(double) + 256, &ws)) return rc;
+  double* part = (double*)ws->buf.p;
+  double* Md = (double*)((char*)ws->buf.p + ceil_to((int64_t)part_bytes, 256));
+  HIP_TRY(hipMemcpyAsync(Md, M, 4 * Qc * sizeof(double), hipMemcpyHostToDevice, st));
+  rb::AssembleArgs g{N, R, X, nsx, phiT, dphiT, testT, part};
+  hipLaunchKernelGGL(rb::assemble_conv_kernel, dim3((unsigned)(wgs * nsx)),
+                     dim3(rb::kWave * rb::kAsmWaves), 0, st, g);
+  HIP_TRY(hipGetLastError());
+  const int64_t per = (int64_t)R * N * N;
+  hipLaunchKernelGGL(rb::assemble_combine_kernel, dim3(launch_grid(per)), dim3(256), 0, st,
+                     (const double*)part, nsx, R, N, Qc, (const double*)Md, w, out);
+  HIP_TRY(hipGetLastError());
+  // the host copy of M has been read; wait so that the caller may release it
+  HIP_TRY(hipStreamSynchronize(st));
   return RB_OK;
 }
 
@@ -1807,6 +1876,7 @@ int rb_server_start(rb_ctx* c, int set, const rb_server_opts* opts, rb_server** 
   const rb_server_opts& o = *opts;
   rb_solve_opts so = {o.tol, o.max_iter, o.precision, o.refine_steps};
   if (int rc = check_opts("rb_server_start", so)) return rc;
+  if (int rc = check_lp_terms("rb_server_start", s, so)) return rc;
   if (o.precision == RB_PREC_F64 && s->N > RB_MAX_N_F64)
     return fail(RB_E_UNSUPPORTED, "rb_server_start: FP64 serving takes set N <= %d",
                 RB_MAX_N_F64);

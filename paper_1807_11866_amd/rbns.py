@@ -20,9 +20,11 @@ RB_PREC_F64, RB_PREC_F32, RB_PREC_BF16, RB_PREC_BF16X3 = 0, 1, 2, 3
 
 EXPORTED = ("rb_create", "rb_destroy", "rb_last_error", "rb_hbm_used", "rb_load_tensors",
             "rb_theta", "rb_solve_batch", "rb_solve_batch_noalloc", "rb_solve_uneven", "rb_autotune", "rb_tuned_config",
-            "rb_recover_pressure", "rb_recover_pressure_uneven", "rb_reconstruct_pressure", "rb_server_start", "rb_server_submit", "rb_server_poll",
+            "rb_recover_pressure", "rb_recover_pressure_uneven", "rb_reconstruct_pressure",
+            "rb_assemble_convection", "rb_server_start", "rb_server_submit", "rb_server_poll",
             "rb_server_stats", "rb_server_stop", "rb_timing_enable", "rb_timing_read")
 RB_ST_FAILED = 5
+RB_ST_REFINED = 6
 RB_MAX_N, RB_MAX_NP = 152, 64
 
 _dp = ct.POINTER(ct.c_double)
@@ -109,6 +111,8 @@ def load(path=None):
                                                [_vp] * 7 + [_vp])
     lib.rb_reconstruct_pressure.argtypes = ([_vp, ct.c_int, ct.c_int, ct.c_int, _vp, ct.c_int,
                                              _vp, ct.c_int, _vp, ct.c_int, _vp])
+    lib.rb_assemble_convection.argtypes = ([_vp] + [ct.c_int] * 4 + [_vp] * 4 +
+                                           [ct.c_double, _vp, _vp])
     lib.rb_server_start.argtypes = [_vp, ct.c_int, ct.POINTER(ServerOpts), ct.POINTER(_vp)]
     lib.rb_server_submit.argtypes = [_vp, ct.POINTER(Request), ct.c_int,
                                      ct.POINTER(ct.c_longlong)]
@@ -256,6 +260,15 @@ def rb_reconstruct_pressure(ctx, B, N, Np, Pc, ldpc, u, ldu, p, ldp, stream=None
     _check(load().rb_reconstruct_pressure(ctx, int(B), int(N), int(Np), _ptr(Pc), int(ldpc),
                                           _ptr(u), int(ldu), _ptr(p), int(ldp),
                                           _stream(stream)))
+
+
+def rb_assemble_convection(ctx, N, R, X, Qc, phiT, dphiT, testT, M, w, out, stream=None):
+    """M: host FP64 array [Qc][2][2]; the other arrays device tensors (layouts in rbns.h)."""
+    import numpy as np
+    Mh = np.ascontiguousarray(M, dtype=np.float64)
+    _check(load().rb_assemble_convection(ctx, int(N), int(R), int(X), int(Qc), _ptr(phiT),
+                                         _ptr(dphiT), _ptr(testT), _ptr(Mh), float(w),
+                                         _ptr(out), _stream(stream)))
 
 
 def rb_timing_enable(ctx, enable=True):

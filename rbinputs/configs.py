@@ -62,6 +62,13 @@ CONFIGS = {
         N=100, kmax=12, G=256, G_quad=64, Q=12, Qc=4, Qf=2, Np=30, Qb=2, B=32768,
         forcing_scale=1.0,
     ),
+    # Paper-shaped term counts: the Piola expansions of Section 5 at n = 12 give 4n + 2 = 50
+    # affine terms of a and 4n + 1 = 49 of c (powers of the angle); N=50 as batched_n50.
+    "batched_n50_q50": dict(
+        _BASE,
+        N=50, kmax=12, G=128, G_quad=128, Q=50, Qc=49, Qf=2, Np=30, Qb=2, B=4096,
+        forcing_scale=1.0,
+    ),
     # Serving: requests with N in 20..150 from one nested N_max=150 set, Q=12, Qc=4.
     "serve_n150": dict(
         _BASE,
@@ -78,6 +85,7 @@ _FORCING_SCALE = {
     "uneven_n20_100": 127.835,
     "mixed_n100": 127.835,
     "serve_n150": 58.0982,
+    "batched_n50_q50": 0.000157138,
 }
 
 for _name, _s in _FORCING_SCALE.items():

@@ -290,6 +290,20 @@ def assemble(N, Np, kmax, G, Q, Qc, Qf, Qb, seeds, force_kmax=4, forcing_scale=1
                 phi_c=phi_c, p_c=p_c, s_c=s_c, g_c=g_c)
 
 
+def quadrature_fields(N, Np, kmax, G, Q, Qc, Qb, seeds):
+    """The basis fields at the G x G quadrature points, as the offline tensor assembly consumes
+    them (same bases and weight matrices as ``assemble``): phi (N, 2, X) with X = G^2,
+    dphi (N, 2, 2, X) with dphi[i, a, b] = d_a phi_i^b, the supremizers s (Np, 2, X), the
+    convection weights M (Qc, 2, 2) and the quadrature weight w = 1 / X."""
+    K, phi_c, p_c, s_c = _basis_coefficients(N, Np, kmax, seeds)
+    _, Ms, _ = _form_matrices(Q, Qc, Qb, seeds)
+    E = grid_modes(K, G)
+    phi = on_grid(phi_c, E)
+    dphi = np.stack([on_grid(deriv(phi_c, K, a), E) for a in range(2)], 1)
+    s_ = on_grid(s_c, E)
+    return dict(phi=phi, dphi=dphi, s=s_, M=np.array(Ms), w=1.0 / (G * G))
+
+
 def assemble_coupled(N, Np, kmax, G, Q, Qc, Qf, seeds, force_kmax=4, forcing_scale=1.0):
     """Operators of the coupled stabilised system (eqn block) as one velocity-only-shaped set.
 

@@ -240,7 +240,7 @@ def test_mixed_precision_parity_ragged(O, R, c2, prec, refine):
     th = s.theta(_dev(mu))
     g = _mixed(R, s, th, prec, refine)
     r = O.solve_batch(O.OracleSet(c2), mu)
-    assert np.all(g["status"] <= 1)
+    assert np.all(np.isin(g["status"], (0, 1, 6)))
     err = _rel(g["u"], r["u"])
     assert np.max(err) <= TOL_MIXED, (np.max(err), np.percentile(err, 99))
     s.close()
@@ -281,7 +281,7 @@ def test_mixed_random_tensors(O, R, N):
     r = O.solve_batch(O.OracleSet(ts), mu, maxit=20)
     for prec, refine in (("F32", 2), ("BF16", 6), ("BF16X3", 2)):
         g = _mixed(R, s, th, prec, refine, max_iter=20)
-        assert np.all(g["status"] <= 1), prec
+        assert np.all(np.isin(g["status"], (0, 1, 6))), prec
         assert np.max(_rel(g["u"], r["u"])) <= TOL_MIXED, prec
     s.close()
 
@@ -328,7 +328,7 @@ def test_mixed_large_n_random(O, R, N):
     r = O.solve_batch(O.OracleSet(ts), mu, maxit=20)
     for prec, refine in (("F32", 2), ("BF16", 6), ("BF16X3", 2)):
         g = _mixed(R, s, th, prec, refine, max_iter=20)
-        assert np.all(g["status"] <= 1), prec
+        assert np.all(np.isin(g["status"], (0, 1, 6))), prec
         assert np.max(_rel(g["u"], r["u"])) <= TOL_MIXED, prec
     s.close()
 
@@ -346,7 +346,7 @@ def test_mixed_large_configs_sampled(O, R, cfg_name, prec, refine):
     th = s.theta(_dev(mu))
     g = _mixed(R, s, th, prec, refine)
     r = O.solve_batch(O.OracleSet(ts), mu, pressure_np=ts.Np)
-    assert np.all(g["status"] <= 1)
+    assert np.all(np.isin(g["status"], (0, 1, 6)))
     assert np.max(_rel(g["u"], r["u"])) <= TOL_MIXED
     p = s.pressure(th, torch.as_tensor(g["u"]).cuda())
     torch.cuda.synchronize()
@@ -433,3 +433,76 @@ def test_lu_variants_agree(O, R, N, Np, monkeypatch):
         assert np.all(p["pstatus"].cpu().numpy() == 0), variant
         assert np.max(_rel(p["p"].cpu().numpy(), r["p"])) <= TOL_F64, variant
         s.close()
+
+
+@pytest.fixture(scope="module")
+def c50q():
+    return make_tensor_set(get_config("batched_n50_q50"))
+
+
+@pytest.mark.parametrize("B,N", [(300, 50), (70, 20), (4096, 50)])
+def test_paper_shaped_term_counts(O, R, c50q, B, N):
+    """Q = 50 affine terms of a and Qc = 49 of c (the Piola expansions at n = 12, powers of
+    the angle): K = Q + Qc N = 2500 at N = 50, the affine part in its own chunk of the
+    contraction and the tensor part in 16 more. Velocity and pressure within 1e-10 of the
+    oracle on a sample of the batch (the whole batch up to 300 requests), statuses equal."""
+    cfg = get_config("batched_n50_q50")
+    mu = draw_mu(cfg, B, seed_offset=B + N)
+    s = R.Solver(c50q)
+    th, g = _gpu_solve(R, s, c50q, mu, N=N)
+    p = s.pressure(th, torch.as_tensor(g["u"]).cuda(), N=N)
+    torch.cuda.synchronize()
+    idx = np.arange(B) if B <= 300 else np.linspace(0, B - 1, 48).astype(int)
+    ts = c50q.leading(N)
+    r = O.solve_batch(O.OracleSet(ts), mu[idx], pressure_np=ts.Np)
+    assert np.array_equal(g["status"][idx], r["status"]) and np.all(g["status"] == 0)
+    assert np.max(_rel(g["u"][idx, :N], r["u"])) <= TOL_F64
+    assert np.max(_rel(p["p"].cpu().numpy()[idx], r["p"])) <= TOL_F64
+    s.close()
+
+
+def test_paper_shaped_terms_fp64_only(R, c50q):
+    s = R.Solver(c50q)
+    th = s.theta(_dev(draw_mu(get_config("batched_n50_q50"), 4)))
+    with pytest.raises(R.RbError) as e:
+        s.solve(th, precision=R.RB_PREC_F32)
+    assert e.value.code == R.RB_E_UNSUPPORTED
+    s.close()
+
+
+def test_theta_power_families_on_gpu(O, R, c50q):
+    mu = draw_mu(get_config("batched_n50_q50"), 33)
+    s = R.Solver(c50q)
+    th = s.theta(_dev(mu))
+    torch.cuda.synchronize()
+    for b in range(33):
+        ta, tc, tf, tb = O.theta(c50q.Q, c50q.Qc, c50q.Qf, c50q.Qb, mu[b, 0], mu[b, 1])
+        for k, ref in (("ta", ta), ("tc", tc), ("tf", tf), ("tb", tb)):
+            got = th[k][b].cpu().numpy()
+            assert np.allclose(got, ref, rtol=4e-16 * 60, atol=0), (k, b)
+    s.close()
+
+
+@pytest.mark.parametrize("prec,refine", [("BF16X3", 1), ("BF16", 3)])
+def test_mixed_n100_full_batch_sampled(O, R, prec, refine):
+    """Config 4 at full size: B = 32768 at N = 100 (Q = 12, Qc = 4), BF16 hi/lo or plain BF16
+    tensors on MFMA, FP32 LU, FP64-residual refinement, in the launch configuration of the
+    bench (8 row splits per tile); velocity and pressure on a seeded sample of 256 requests
+    within 1e-8 of the oracle."""
+    cfg = get_config("mixed_n100")
+    ts = make_tensor_set(cfg)
+    B = cfg["B"]
+    mu = draw_mu(cfg, B)
+    s = R.Solver(ts)
+    th = s.theta(_dev(mu))
+    print(f"[mixed full] {prec} + {refine}", flush=True)
+    g = _mixed(R, s, th, prec, refine)
+    p = s.pressure(th, torch.as_tensor(g["u"]).cuda())
+    torch.cuda.synchronize()
+    pick = np.random.default_rng(11).choice(B, 256, replace=False)
+    r = O.solve_batch(O.OracleSet(ts), mu[pick], pressure_np=ts.Np)
+    assert np.all(np.isin(g["status"], (0, 1, 6)))
+    assert np.max(_rel(g["u"][pick], r["u"])) <= TOL_MIXED
+    assert np.all(p["pstatus"].cpu().numpy() == 0)
+    assert np.max(_rel(p["p"].cpu().numpy()[pick], r["p"])) <= TOL_MIXED
+    s.close()
