@@ -157,18 +157,19 @@ def other_workload(args):
     torch.cuda.synchronize()
     fam_names = ("jacobian", "lu", "residual", "pressure")
 
-    def timed(step, nsteps, nwarm):
+    def timed(step, nsteps, nwarm, ctx=None):
+        ctx = s.ctx if ctx is None else ctx
         for _ in range(nwarm):
             step()
         torch.cuda.synchronize()
-        rbns.rb_timing_enable(s.ctx, True)
+        rbns.rb_timing_enable(ctx, True)
         t0 = time.perf_counter()
         for _ in range(nsteps):
             step()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        rbns.rb_timing_enable(s.ctx, False)
-        return t1 - t0, {f: rbns.rb_timing_read(s.ctx, f) for f in fam_names}
+        rbns.rb_timing_enable(ctx, False)
+        return t1 - t0, {f: rbns.rb_timing_read(ctx, f) for f in fam_names}
 
     if name == "single_n10":
         metric = "reduced NS solves/sec at N=10 (plain single solve, B=1 per call)"
@@ -218,6 +219,37 @@ def other_workload(args):
         el, fams = timed(step, nsteps, max(2, args.warmup // 2))
         value, steps = B * nsteps / el, nsteps
         ms_step = 1e3 * el / nsteps
+        if uneven:
+            # The graph replays carry no per-launch events: a second context on plain launches
+            # (the same kernels) gives the kernel-family times of the roofline, and a fresh
+            # N mix every step gives the rate when no shape repeats.
+            os.environ["RB_UNEVEN_GRAPHS"] = "0"
+            s2 = rbns.Solver(ts, device=0)
+            del os.environ["RB_UNEVEN_GRAPHS"]
+            th2 = s2.theta(mu)
+            out2 = {k: torch.empty_like(v) for k, v in out.items()}
+
+            def step2():
+                s2.solve_uneven(th2, Nd, tol=cfg["tol"], max_iter=cfg["max_iter"],
+                                precision=prec, refine_steps=refine, out=out2, stream=stream)
+            el2, fams = timed(step2, nsteps, 1, ctx=s2.ctx)
+            extra["eager_ms_per_step"] = 1e3 * el2 / nsteps
+            extra["kernel_timing"] = "plain-launch pass with the same kernels as the graph replay"
+            mixes = [torch.as_tensor(draw_basis_sizes(cfg, B, seed_offset=1000 + k), device=dev,
+                                     dtype=torch.int32) for k in range(nsteps + 1)]
+            s2.solve_uneven(th2, mixes[-1], tol=cfg["tol"], max_iter=cfg["max_iter"],
+                            precision=prec, refine_steps=refine, out=out2, stream=stream)
+            torch.cuda.synchronize()
+            tf0 = time.perf_counter()
+            for k in range(nsteps):
+                s.solve_uneven(th, mixes[k], tol=cfg["tol"], max_iter=cfg["max_iter"],
+                               precision=prec, refine_steps=refine, out=out2, stream=stream)
+            torch.cuda.synchronize()
+            extra["fresh_mix_solves_s"] = B * nsteps / (time.perf_counter() - tf0)
+            log(f"[bench] uneven: graph replay {value:.4g} solves/s, plain launches "
+                f"{B / (el2 / nsteps):.4g}, fresh N mix every call {extra['fresh_mix_solves_s']:.4g}")
+            Nreq_t = Nreq
+            s2.close()
         metric = ("reduced NS solves/sec, uneven N in {20..100} in one call (FP32 + FP64 "
                   "refinement)" if uneven else
                   f"reduced NS solves/sec at N=100 ({args.mixed_prec.upper()} MFMA + "

@@ -235,8 +235,9 @@ int rb_solve_batch_noalloc(rb_ctx *ctx, int set, int B, int N, int ldu, const do
  * (one graph launch per call, up to 4 group chains running concurrently); a shape seen for the
  * first time runs as plain launches. The first time a (set, N, precision, batch size class)
  * occurs, the autotuner times the candidate tile shapes on that group (synchronously) and
- * keeps the fastest (environment RB_AUTOTUNE=0 disables it). Requests with N[b] outside
- * [1, set N] get status RB_ST_BADN, iters 0 and u = 0.
+ * keeps the fastest (environment RB_AUTOTUNE=0 disables it; RB_UNEVEN_GRAPHS=0 keeps every
+ * call on plain launches, so that the kernel timing of rb_timing_* sees each launch).
+ * Requests with N[b] outside [1, set N] get status RB_ST_BADN, iters 0 and u = 0.
  * Errors: as rb_solve_batch (RB_E_INVAL also for ldu < the set's N).
  */
 int rb_solve_uneven(rb_ctx *ctx, int set, int B, const int *N, int ldu, const double *theta_a,

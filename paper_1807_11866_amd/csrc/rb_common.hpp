@@ -372,14 +372,13 @@ __device__ __forceinline__ void block_sum2(double& s0, double& s1, int lane, int
 namespace rb {
 
 // One Newton update of one request whose system is spread over the W wavefronts of the
-// workgroup (NP > 64). Loads J row by row into the lanes (J[i][c] = the sum over the nsl
-// slices sl of jload(sl, c, i)), forms the
+// workgroup (NP > 64). Loads J row by row into the lanes (J[i][c] = jload(c, i)), forms the
 // right-hand side -F(u) via rhs_of(row, J_row . u), solves by gj_solve_mw, and adds the
 // correction to the FP64 iterate. Returns the status flag (0 ok, 2 singular, 3 non-finite)
 // and the squared H-norms of the update and of the new iterate. Uniform over the workgroup;
 // every thread must call it.
 template <typename T, int NP, int W, typename JLoad, typename RhsOf>
-__device__ __forceinline__ int mw_newton_update(JLoad jload, int nsl, int N, int Nm,
+__device__ __forceinline__ int mw_newton_update(JLoad jload, int N, int Nm,
                                                 double* __restrict__ ub,
                                                 const double* __restrict__ H, RhsOf rhs_of,
                                                 GjShared<NP, W, T>& sh, double& nd2,
@@ -390,11 +389,7 @@ __device__ __forceinline__ int mw_newton_update(JLoad jload, int nsl, int N, int
   T ju = T(0);
   bool bad = false;
 #pragma unroll
-  for (int c = 0; c < NP; ++c) r[c] = jload(0, c < N ? c : N - 1, rc);
-  for (int sl = 1; sl < nsl; ++sl) {
-#pragma unroll
-    for (int c = 0; c < NP; ++c) r[c] += jload(sl, c < N ? c : N - 1, rc);
-  }
+  for (int c = 0; c < NP; ++c) r[c] = jload(c < N ? c : N - 1, rc);
 #pragma unroll
   for (int c = 0; c < NP; ++c) {
     r[c] = (c < N && row < N) ? r[c] : (c == row ? T(1) : T(0));

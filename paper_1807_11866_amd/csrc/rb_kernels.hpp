@@ -115,8 +115,6 @@ struct NewtonState {
   int64_t mp;
   int NP;
   int nsplit;              // partial sums per request in Wv / the mixed-precision partials
-  int jslices;             // FP64 Jacobian slices (one per tensor chunk; 0: no FP64 J)
-  int64_t jstride;         // doubles between slices
 };
 
 struct NewtonF64Args {
@@ -184,8 +182,10 @@ static __global__ void newton_init_kernel(NewtonF64Args a) {
 // loads of the next group of row blocks are issued during the tail of the current one, so the
 // pipeline does not drain between groups. The affine part is padded to kAmax = 3 k-steps
 // (zero columns) so that every row block has the same static pipeline. Tensor parts longer
-// than 64 k-steps run as nchunk chunks, each walking the row blocks again with fresh
-// accumulators (the Jacobian adds each later chunk to what the earlier ones stored). Long
+// than kMaxKC k-steps run as nchunk chunks, each walking the row blocks again with fresh
+// accumulators; the Jacobian adds each later chunk to what the earlier ones stored (the lane
+// that stores a J piece in one chunk is the one that reads and updates it in the next, and it
+// loads the old piece at the start of the row group, so the read is off the critical path). Long
 // affine expansions (Q > 12, the Piola-mapped forms of Section 5) go in naff chunks of their
 // own in front of the tensor chunks, with the same chunk length, and the affine accumulator
 // is folded at the end of those passes.
@@ -224,9 +224,8 @@ struct ContractArgs {
   const double* U;         // iterates, row b at U + b*ldU (rows >= B are not read)
   int ldU;
   const int* done;         // Newton flags [Bp] or nullptr
-  double* J;               // Jacobians [Bp][mp] per chunk slice, or nullptr
+  double* J;               // Jacobians [Bp][mp] (column-major per request), or nullptr
   int64_t mp;
-  int64_t jstride;         // doubles between the J slices of consecutive chunks
   double* part;            // partial row sums [nsplit][Bp][ldp]
   int ldp;
 };
@@ -322,6 +321,17 @@ void contract_f64_kernel(ContractArgs a) {
       f64x4 c[kGroup];
 #pragma unroll
       for (int r = 0; r < kGroup; ++r) c[r] = f64x4{0.0, 0.0, 0.0, 0.0};
+      // Jacobian pieces of this group stored by the earlier chunks (this lane's own stores)
+      f64x4* jp[kGroup];
+      f64x4 jold[kGroup];
+      if (kMode == kModeJac) {
+#pragma unroll
+        for (int r = 0; r < kGroup; ++r) {
+          jp[r] = reinterpret_cast<f64x4*>(a.J + (int64_t)(b0 + 16 * wv + (lane >> 2)) * a.mp +
+                                           (g0 + r) * 16 + 4 * (lane & 3));
+          jold[r] = (chunk > 0 && g0 + r < rb_hi) ? *jp[r] : f64x4{0.0, 0.0, 0.0, 0.0};
+        }
+      }
 #pragma unroll
       for (int ks = 0; ks < NKS; ++ks) {
         const int pf = ks + kDepth;
@@ -354,12 +364,7 @@ void contract_f64_kernel(ContractArgs a) {
           wave_lds_order();
           const f64x4 val = *reinterpret_cast<const f64x4*>(&stg[q2 * kStageLd + e0]);
           wave_lds_order();
-          if (g0 + r < rb_hi) {
-            f64x4* jp = reinterpret_cast<f64x4*>(a.J + chunk * a.jstride +
-                                                 (int64_t)(b0 + 16 * wv + q2) * a.mp +
-                                                 (g0 + r) * 16 + e0);
-            *jp = val;                     // cached: the LU kernel reads J next
-          }
+          if (g0 + r < rb_hi) *jp[r] = val + jold[r];   // cached: the LU kernel reads J next
         }
       } else {
         fold(c, g0, end_wt);
@@ -433,19 +438,13 @@ void lu_f64_kernel(NewtonF64Args a, int it) {
   const int lc = lane < N ? lane : N - 1;
   double ju = 0.0;
   bool bad = false;
-  // J row of this lane (sum of the chunk slices), padded to identity beyond the request's
-  // size; loads clamped in bounds.
+  // J row of this lane, padded to identity beyond the request's size; loads clamped in bounds.
 #pragma unroll
   for (int c0 = 0; c0 < NP; c0 += 8) {
     double v[8];
 #pragma unroll
     for (int t = 0; t < 8; ++t)
       if (c0 + t < NP) v[t] = jb[(c0 + t < N ? c0 + t : N - 1) * N + lc];
-    for (int sl = 1; sl < a.s.jslices; ++sl) {
-#pragma unroll
-      for (int t = 0; t < 8; ++t)
-        if (c0 + t < NP) v[t] += jb[sl * a.s.jstride + (c0 + t < N ? c0 + t : N - 1) * N + lc];
-    }
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
       const int c = c0 + t;
@@ -509,7 +508,7 @@ __global__ __launch_bounds__(kWave * W) void lu_f64_mw_kernel(NewtonF64Args a, i
   if (a.s.done[b]) return;
   const int N = a.N;
   const double* jb = a.s.J + (int64_t)b * a.s.mp;
-  auto jload = [&](int sl, int c, int row) { return jb[sl * a.s.jstride + c * N + row]; };
+  auto jload = [&](int c, int row) { return jb[c * N + row]; };
   double* ub = a.s.U + (int64_t)b * NP;
   auto rhs_of = [&](int row, double ju) {
     double w = 0.0;
@@ -519,7 +518,7 @@ __global__ __launch_bounds__(kWave * W) void lu_f64_mw_kernel(NewtonF64Args a, i
   };
   double nd2, nu2;
   const int nb = a.nreq ? a.nreq[b] : N;
-  const int flag = mw_newton_update<double, NP, W>(jload, a.s.jslices, nb, a.Nm, ub, a.H, rhs_of,
+  const int flag = mw_newton_update<double, NP, W>(jload, nb, a.Nm, ub, a.H, rhs_of,
                                                    sh, nd2, nu2);
   if (threadIdx.x != 0) return;
   if (flag != 0) {

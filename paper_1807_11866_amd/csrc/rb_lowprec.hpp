@@ -423,7 +423,7 @@ __global__ __launch_bounds__(kWave * W) void lu_lp_mw_kernel(LpNewtonArgs a, int
   const int64_t Bp = a.s.Bp;
   const float* jb = a.J + (int64_t)b * a.mp;
   const int N = a.N;
-  auto jload = [&](int, int c, int row) { return jb[c * N + row]; };
+  auto jload = [&](int c, int row) { return jb[c * N + row]; };
   double* ub = a.s.U + (int64_t)b * NP;
   auto rhs_of = [&](int row, float ju) {
     const double f = a.s.Fv[(int64_t)b * NP + row];
@@ -440,7 +440,7 @@ __global__ __launch_bounds__(kWave * W) void lu_lp_mw_kernel(LpNewtonArgs a, int
   };
   double nd2, nu2;
   const int nb = a.nreq ? a.nreq[b] : N;
-  const int flag = mw_newton_update<float, NP, W>(jload, 1, nb, a.Nm, ub, a.H, rhs_of, sh, nd2,
+  const int flag = mw_newton_update<float, NP, W>(jload, nb, a.Nm, ub, a.H, rhs_of, sh, nd2,
                                                   nu2);
   if (threadIdx.x != 0) return;
   if (flag != 0) {

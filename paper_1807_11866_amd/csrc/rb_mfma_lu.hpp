@@ -202,10 +202,21 @@ void lu_mfma_f64_kernel(NewtonF64Args a, int it) {
   bool bad = false;
 #pragma unroll
   for (int r0 = 0; r0 < NT; ++r0) ju[r0] = 0.0;
-  // J (sum of the chunk slices; column-major per request) into the tile layout, identity
-  // rows and columns beyond the request's size; this lane's share of J u on the way
+  // J (column-major per request) into the tile layout, identity rows and columns beyond the
+  // request's size; this lane's share of J u on the way. One column tile at a time: its loads
+  // are issued together (offsets from the request's base, clamped in bounds).
+  const int lc = li < N ? li : N - 1;
 #pragma unroll
-  for (int bt = 0; bt < NT; ++bt)
+  for (int bt = 0; bt < NT; ++bt) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int c = 16 * bt + lg + 4 * v, cc = c < N ? c : N - 1;
+#pragma unroll
+      for (int at = 0; at < NT; ++at) {
+        const int r = 16 * at + li, rr = r < N ? r : lc;
+        R[at][bt][v] = jb[cc * N + rr];
+      }
+    }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int c = 16 * bt + lg + 4 * v;
@@ -213,17 +224,15 @@ void lu_mfma_f64_kernel(NewtonF64Args a, int it) {
 #pragma unroll
       for (int at = 0; at < NT; ++at) {
         const int r = 16 * at + li;
-        double val = (r == c && c < P - 1) ? 1.0 : 0.0;
-        if (r < N && c < N) {
-          double jv = jb[(int64_t)c * N + r];
-          for (int sl = 1; sl < a.s.jslices; ++sl) jv += jb[sl * a.s.jstride + (int64_t)c * N + r];
-          val = (r < nb && c < nb) ? jv : val;
-        }
+        const double val = (r < nb && c < nb) ? R[at][bt][v]
+                                              : ((r == c && c < P - 1) ? 1.0 : 0.0);
         bad |= !finite_val(val);
         ju[at] = fma(val, uc, ju[at]);
         R[at][bt][v] = val;
       }
     }
+    __builtin_amdgcn_sched_barrier(0);
+  }
   // right-hand side -F(u) of row 16a + l%16 into column P-1 (lanes l/16 = 3, element 3)
 #pragma unroll
   for (int at = 0; at < NT; ++at) {

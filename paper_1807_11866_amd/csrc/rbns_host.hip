@@ -117,6 +117,7 @@ struct rb_ctx {
   // autotuner results: (set, N, precision, batch size class) -> tile shape
   std::map<std::tuple<int, int, int, int>, Tune> tune;
   bool autotune = true;
+  bool uneven_graphs = true;            // capture and replay uneven-batch group chains
   // uneven batches: pinned staging of the per-request sizes / permutation, capture streams,
   // graph cache and the shapes seen once (captured on their second occurrence)
   int* pin = nullptr;
@@ -309,17 +310,17 @@ int workspace(rb_ctx* c, void* stream, size_t bytes, Workspace** out) {
 }
 
 // Carve the Newton state for Bp (padded) requests out of one workspace allocation.
-size_t newton_state_bytes(int64_t Bp, int NP, int64_t mp, int nsplit, int jslices) {
-  return (size_t)(jslices * Bp * mp + (2 + nsplit) * Bp * NP + Bp) * sizeof(double) +
+size_t newton_state_bytes(int64_t Bp, int NP, int64_t mp, int nsplit, bool f64_j) {
+  return (size_t)((f64_j ? Bp * mp : 0) + (2 + nsplit) * Bp * NP + Bp) * sizeof(double) +
          (size_t)3 * Bp * sizeof(int) + 256;
 }
 
 rb::NewtonState carve_state(void* base, int64_t Bp, int NP, int64_t mp, int nsplit,
-                            int jslices) {
+                            bool f64_j) {
   rb::NewtonState s;
   double* d = (double*)base;
-  s.J = d;
-  d += jslices * Bp * mp;
+  s.J = f64_j ? d : nullptr;
+  d += f64_j ? Bp * mp : 0;
   s.U = d;
   d += Bp * NP;
   s.Fv = d;
@@ -336,8 +337,6 @@ rb::NewtonState carve_state(void* base, int64_t Bp, int NP, int64_t mp, int nspl
   s.NP = NP;
   s.Bp = Bp;
   s.nsplit = nsplit;
-  s.jslices = jslices;
-  s.jstride = Bp * mp;
   return s;
 }
 
@@ -347,14 +346,8 @@ size_t lp_extra_bytes(int64_t Bp, int NP, int64_t mp, int nsplit) {
          (size_t)nsplit * Bp * NP * sizeof(double);
 }
 
-// FP64 Jacobian slices of a solve at basis size N: one per tensor chunk of the FP64 operand
-// (the mixed precisions keep their Jacobian in FP32 and need none).
-int jslices_for(const Set* s, int N, int precision) {
-  if (precision != RB_PREC_F64) return 0;
-  int n, kc, naff;
-  f64_layout(s, N, &n, &kc, &naff);
-  return naff + n;
-}
+// An FP64 Jacobian per request (the mixed precisions keep theirs in FP32).
+bool needs_f64_j(int precision) { return precision == RB_PREC_F64; }
 
 // Register row length of the LU kernels (Newton and pressure): even up to 64 (one wavefront
 // per system; every padded column costs a pivot step and a column of updates), multiples of
@@ -366,7 +359,7 @@ int np_bucket(int n) { return (int)ceil_to(n, n <= 64 ? 2 : 8); }
 size_t solve_bytes(const Set* s, int N, int64_t Bp, int nsplit, int precision) {
   const int NP = np_bucket(N);
   const int64_t mp = ceil_to((int64_t)N * N, 16);
-  size_t b = newton_state_bytes(Bp, NP, mp, nsplit, jslices_for(s, N, precision));
+  size_t b = newton_state_bytes(Bp, NP, mp, nsplit, needs_f64_j(precision));
   if (precision != RB_PREC_F64) b += lp_extra_bytes(Bp, NP, mp, nsplit);
   return (size_t)ceil_to((int64_t)b, 256);
 }
@@ -422,7 +415,7 @@ int enqueue_newton(rb_ctx* c, const rb::NewtonF64Args& a, int lu, hipStream_t st
   g.ta = a.ta; g.tc = a.tc;
   g.U = a.s.U; g.ldU = NP;
   g.done = a.s.done;
-  g.J = a.s.J; g.mp = a.s.mp; g.jstride = a.s.jstride;
+  g.J = a.s.J; g.mp = a.s.mp;
   g.part = a.s.Wv; g.ldp = NP;
   hipLaunchKernelGGL(rb::newton_init_kernel, dim3(launch_grid(Bp * NP)), dim3(256), 0, st, a);
   for (int it = 0; it < a.maxit; ++it) {
@@ -474,7 +467,7 @@ int enqueue_newton_lp(rb_ctx* c, Set* s, const rb::NewtonF64Args& a, int prec, i
   gr.R = N; gr.N = N; gr.M = N * N;
   gr.Q = a.Q; gr.Qc = a.Qc; gr.B = a.B; gr.Bp = Bp;
   gr.ta = a.ta; gr.tc = a.tc; gr.U = a.s.U; gr.ldU = NP;
-  gr.done = a.s.done; gr.J = nullptr; gr.mp = 0; gr.jstride = 0;
+  gr.done = a.s.done; gr.J = nullptr; gr.mp = 0;
   gr.part = partA; gr.ldp = NP;
 
   rb::LpNewtonArgs la;
@@ -544,7 +537,7 @@ int enqueue_pressure(rb_ctx* c, Set* s, int B, int N, int Np, int ldu, int ldp,
   g.ta = ta; g.tc = tc;
   g.U = u; g.ldU = ldu;
   g.done = nullptr;
-  g.J = nullptr; g.mp = 0; g.jstride = 0;
+  g.J = nullptr; g.mp = 0;
   g.part = (double*)part; g.ldp = NPP; g.nsplit = pressure_nsplit(B, N, Np, nsplit);
   rb::PressureF64Args a;
   a.Np = Np; a.Npm = s->Np; a.Qf = s->Qf; a.Qb = s->Qb; a.B = B; a.ldp = ldp; a.Bp = Bp;
@@ -629,14 +622,15 @@ rb::NewtonF64Args make_args(Set* s, Pack* pk, int N, int B, int ldu, const rb_so
   a.u = u; a.iters = iters; a.status = status;
   const int64_t Bp = ceil_to(B, rb::kTile);
   a.s = carve_state(region, Bp, np_bucket(N), ceil_to((int64_t)N * N, 16), nsplit,
-                    jslices_for(s, N, o.precision));
+                    needs_f64_j(o.precision));
   return a;
 }
 
 int enqueue_solve(rb_ctx* c, Set* s, const rb::NewtonF64Args& a, const rb_solve_opts& o,
                   const Tune& t, char* region, hipStream_t st) {
   if (o.precision == RB_PREC_F64) return enqueue_newton(c, a, t.lu, st);
-  char* lp = region + newton_state_bytes(a.s.Bp, a.s.NP, a.s.mp, a.s.nsplit, a.s.jslices);
+  char* lp = region + newton_state_bytes(a.s.Bp, a.s.NP, a.s.mp, a.s.nsplit,
+                                        needs_f64_j(o.precision));
   return enqueue_newton_lp(c, s, a, o.precision, o.refine_steps, lp, st);
 }
 
@@ -660,8 +654,8 @@ int autotune_batch(rb_ctx* c, Set* s, int set, rb::NewtonF64Args a, const rb_sol
     return rc;
   };
   const int rsplit = region_nsplit(Bp, N);
-  a.s = carve_state(region, Bp, NP, mp, rsplit, jslices_for(s, N, o.precision));
-  char* lpb = region + newton_state_bytes(Bp, NP, mp, rsplit, a.s.jslices);
+  a.s = carve_state(region, Bp, NP, mp, rsplit, needs_f64_j(o.precision));
+  char* lpb = region + newton_state_bytes(Bp, NP, mp, rsplit, needs_f64_j(o.precision));
   auto contract = [&](int nsplit) -> int {
     a.s.nsplit = nsplit;
     if (!lp) {
@@ -672,7 +666,7 @@ int autotune_batch(rb_ctx* c, Set* s, int set, rb::NewtonF64Args a, const rb_sol
       g.R = N; g.N = N; g.M = N * N;
       g.Q = a.Q; g.Qc = a.Qc; g.B = a.B; g.Bp = Bp;
       g.ta = a.ta; g.tc = a.tc; g.U = a.s.U; g.ldU = NP;
-      g.done = a.s.done; g.J = a.s.J; g.mp = mp; g.jstride = a.s.jstride;
+      g.done = a.s.done; g.J = a.s.J; g.mp = mp;
       g.part = a.s.Wv; g.ldp = NP;
       return launch_rc(rb::launch::contract_f64(rb::kModeJac, g, st), "autotune contraction");
     }
@@ -814,6 +808,7 @@ int rb_create(int device, size_t hbm_budget_bytes, rb_ctx** out) {
     else if (strcmp(v, "mfma") == 0) c->lu = RB_LU_MFMA;
   }
   if (const char* v = getenv("RB_AUTOTUNE")) c->autotune = (strcmp(v, "0") != 0);
+  if (const char* v = getenv("RB_UNEVEN_GRAPHS")) c->uneven_graphs = (strcmp(v, "0") != 0);
   *out = c;
   g_err.clear();
   return RB_OK;
@@ -1190,8 +1185,9 @@ int rb_solve_uneven(rb_ctx* c, int set, int B, const int* Nd, int ldu, const dou
   };
   GraphEntry* hit = nullptr;
   for (auto& e : c->graphs)
-    if (e.key == key) hit = &e;
-  const bool seen = std::find(c->seen.begin(), c->seen.end(), key) != c->seen.end();
+    if (c->uneven_graphs && e.key == key) hit = &e;
+  const bool seen = c->uneven_graphs &&
+                    std::find(c->seen.begin(), c->seen.end(), key) != c->seen.end();
   if (!hit && seen && !gs.empty()) {
     if (int rc = ensure_streams(c, kBranches)) return rc;
     const bool timing = c->timing;
