@@ -188,6 +188,13 @@ int rb_theta(rb_ctx *ctx, int set, int B, const double *mu, double *theta_a, dou
  * step) until an update is below tol (status RB_ST_CONVERGED, else RB_ST_REFINED or
  * RB_ST_MAXIT, see RB_ST_REFINED). iters
  * counts both kinds of updates.
+ * Schedule (FP64, N <= 64 with the readlane LU): the first K Newton iterations run as launch
+ * pairs over the whole batch and the remaining max_iter - K in one launch that steps each
+ * 64-request tile until its requests are done; K is the largest iteration count of the last
+ * finished call with the same set and N (read back without blocking; max_iter at first), or
+ * RB_NEWTON_K in the environment of rb_create (0: all max_iter iterations as launch pairs,
+ * n > 0: K = n). Results do not depend on K, bit for bit. Under stream capture the schedule
+ * keeps all max_iter pairs.
  * Errors: RB_E_INVAL (NULL, B < 0, N or ldu out of range, bad opts), RB_E_NOMEM,
  * RB_E_UNSUPPORTED (RB_PREC_F64 with N > RB_MAX_N_F64), RB_E_DEVICE. B == 0 is a no-op.
  */
@@ -199,7 +206,9 @@ int rb_solve_batch(rb_ctx *ctx, int set, int B, int N, int ldu, const double *th
 /*
  * rb_solve_batch_noalloc: rb_solve_batch for callers that cannot allocate device memory: code
  * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc. Same
- * arguments, same kernels and tile shapes, same results as rb_solve_batch. The Newton state
+ * arguments, same kernels and tile shapes, same results as rb_solve_batch (it runs all
+ * max_iter Newton iterations as launch pairs: the iteration history would need an
+ * allocation). The Newton state
  * (Jacobians, iterates, partial sums, flags) lives in one static device array of
  * RB_NOALLOC_SCRATCH_BYTES per device, held from library load to process exit, instead of a
  * per-stream workspace; the call allocates nothing (no hipMalloc / hipFree / library

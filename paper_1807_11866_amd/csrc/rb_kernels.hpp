@@ -136,6 +136,8 @@ struct NewtonF64Args {
   double* u;               // [B][ldu]
   int* iters;              // [B]
   int* status;             // [B]
+  int* max_iters;          // largest iteration count of the batch (set by the final kernel), or
+                           // nullptr
   NewtonState s;
 };
 
@@ -165,6 +167,7 @@ static __global__ void newton_init_kernel(NewtonF64Args a) {
       a.s.status[b] = 1;
     }
   }
+  if (a.max_iters && blockIdx.x == 0 && threadIdx.x == 0) *a.max_iters = 0;
 }
 
 // ------------------------------------------------------------------ contraction ------
@@ -423,13 +426,12 @@ void contract_f64_kernel(ContractArgs a) {
 
 // One wavefront per request: residual F(u) = (J u + A u)/2 - f, pivoted LU solve of
 // J delta = -F(u), update, and the stopping test ||delta||_H <= tol ||u||_H.
+// The Newton step of request b (wave-uniform, b < B, not done) by the calling wavefront;
+// prow: NP + 8 doubles of LDS owned by the wavefront.
 template <int NP, bool kLdsBcast>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(!kLdsBcast && NP <= 56 ? 4 : 1)))
-void lu_f64_kernel(NewtonF64Args a, int it) {
-  __shared__ double prow[kWaves][NP + 8];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int b = __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves + wv);   // wave-uniform
-  if (b >= a.B || a.s.done[b]) return;
+__device__ __forceinline__ void lu_f64_request(const NewtonF64Args& a, int it, int b,
+                                               double* prow) {
+  const int lane = threadIdx.x & 63;
   const int N = a.N;
   const int nb = a.nreq ? a.nreq[b] : N;   // this request's size; rows/columns beyond: identity
   const double* jb = a.s.J + (int64_t)b * a.s.mp;
@@ -466,7 +468,7 @@ void lu_f64_kernel(NewtonF64Args a, int it) {
   bad |= !finite_val(rhs);
   int flag = __builtin_amdgcn_readfirstlane(__any(bad) ? 3 : 0);
   double dx = 0.0;
-  if (flag == 0) flag = lu_solve_rows<NP, kLdsBcast>(r, rhs, lane, &prow[wv][0], dx);
+  if (flag == 0) flag = lu_solve_rows<NP, kLdsBcast>(r, rhs, lane, prow, dx);
   if (flag == 0) {
     const double uo = lane < N ? ub[lane] : 0.0;
     const double un = uo + (lane < N ? dx : 0.0);
@@ -498,6 +500,16 @@ void lu_f64_kernel(NewtonF64Args a, int it) {
     a.s.status[b] = flag;
     a.s.done[b] = 1;
   }
+}
+
+template <int NP, bool kLdsBcast>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(!kLdsBcast && NP <= 56 ? 4 : 1)))
+void lu_f64_kernel(NewtonF64Args a, int it) {
+  __shared__ double prow[kWaves][NP + 8];
+  const int wv = threadIdx.x >> 6;
+  const int b = __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves + wv);   // wave-uniform
+  if (b >= a.B || a.s.done[b]) return;
+  lu_f64_request<NP, kLdsBcast>(a, it, b, &prow[wv][0]);
 }
 
 // NP > 64: one request per workgroup of W wavefronts (Gauss-Jordan over the workgroup).
@@ -535,6 +547,7 @@ __global__ __launch_bounds__(kWave * W) void lu_f64_mw_kernel(NewtonF64Args a, i
 
 static __global__ void newton_final_kernel(NewtonF64Args a) {
   const int NP = a.s.NP;
+  uint32_t most = 0;
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < (int64_t)a.B * a.ldu;
        idx += (int64_t)gridDim.x * blockDim.x) {
     const int64_t b = idx / a.ldu;
@@ -543,7 +556,12 @@ static __global__ void newton_final_kernel(NewtonF64Args a) {
     if (i == 0) {
       a.iters[b] = a.s.iters[b];
       a.status[b] = a.s.status[b];
+      most = max(most, (uint32_t)a.s.iters[b]);
     }
+  }
+  if (a.max_iters) {                       // one atomic per wavefront
+    most = wave_max_u32(most);
+    if ((threadIdx.x & 63) == 0 && most > 0) atomicMax(a.max_iters, (int)most);
   }
 }
 

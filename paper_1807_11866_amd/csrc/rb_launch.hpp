@@ -18,6 +18,13 @@ int contract_f64(int mode, const ContractArgs& g, hipStream_t st);
 // workgroup per system.
 // `variant` is one of RB_LU_*; RB_LU_MFMA beyond RB_LU_MFMA_MAX_N falls back to readlane.
 int lu_f64(int NP, const NewtonF64Args& a, int it, int variant, hipStream_t st);
+// The RB_LU_* variant that lu_f64 runs for this NP, N and requested variant (RB_LU_AUTO
+// resolved; -1 for the workgroup LU of NP > 64).
+int lu_f64_variant(int NP, int N, int variant);
+// The Newton iterations it0 .. maxit-1 of the batch in one launch (rb_tail.hpp): for batches
+// whose regular launches use the readlane LU (NP <= 64).
+int newton_tail_f64(int NP, const ContractArgs& g, const NewtonF64Args& a, int it0,
+                    hipStream_t st);
 int plu_f64(int NPP, const PressureF64Args& a, int variant, hipStream_t st);
 // Low-precision contraction, prec = RB_PREC_F32 (KT even <= 64 or a multiple of 4 <= 152),
 // RB_PREC_BF16 (KT <= 20) or RB_PREC_BF16X3 (KT <= 20).

@@ -36,10 +36,17 @@ static int go_plu(const PressureF64Args& a, bool lds, hipStream_t st) {
 #define RB_NP_ODD2(X) X(2) X(6) X(10) X(14) X(18) X(22) X(26) X(30) X(34) X(38) X(42) X(46) \
   X(50) X(54) X(58) X(62)
 
+int lu_f64_variant(int NP, int N, int variant) {
+  if (NP > 64) return -1;
+  if (variant == RB_LU_AUTO) variant = N <= RB_LU_AUTO_MFMA_N ? RB_LU_MFMA : RB_LU_READLANE;
+  if (variant == RB_LU_MFMA && N > RB_LU_MFMA_MAX_N) variant = RB_LU_READLANE;
+  return variant;
+}
+
 int lu_f64(int NP, const NewtonF64Args& a, int it, int variant, hipStream_t st) {
-  if (NP > 64) return lu_f64_mw(NP, a, it, st);
-  if (variant == RB_LU_AUTO) variant = a.N <= RB_LU_AUTO_MFMA_N ? RB_LU_MFMA : RB_LU_READLANE;
-  if (variant == RB_LU_MFMA && a.N <= RB_LU_MFMA_MAX_N) return lu_f64_mfma(a, it, st);
+  variant = lu_f64_variant(NP, a.N, variant);
+  if (variant < 0) return lu_f64_mw(NP, a, it, st);
+  if (variant == RB_LU_MFMA) return lu_f64_mfma(a, it, st);
   const bool lds = variant == RB_LU_LDS;
   switch (NP) {
 #define RB_C(n) case n: return go_lu<n>(a, it, lds, st);

@@ -68,6 +68,18 @@ struct Pack {              // packed MFMA operand for one basis size
   int naff = 0;            // long expansions: affine chunks of the same length (nks_s of them)
 };
 
+// Newton iteration counts of the FP64 batches of one basis size: the final kernel leaves the
+// batch's largest count in `dev`, which is copied to `host` behind `ev`; a later batch reads it
+// once the copy has landed (never waiting for it) and runs that many regular iterations before
+// the tail launch.
+struct NewtonHist {
+  DevBuf dev;
+  int* host = nullptr;
+  hipEvent_t ev = nullptr;
+  bool pending = false;
+  int k = 0;                               // learned count (0: none yet)
+};
+
 struct Set {
   int N = 0, Q = 0, Qc = 0, Qf = 0, Np = 0, Qb = 0;
   DevBuf A, C, F, H, BpT, Asv, Csv, Fs;
@@ -75,6 +87,7 @@ struct Set {
   std::map<int, Pack> solve_f64;                     // key: N
   std::map<std::pair<int, int>, Pack> press_f64;     // key: (N, Np)
   std::map<std::pair<int, int>, Pack> solve_lp;      // key: (N, RB_PREC_*)
+  std::map<int, NewtonHist> hist;                    // key: N
 };
 
 struct Workspace {
@@ -118,6 +131,7 @@ struct rb_ctx {
   std::map<std::tuple<int, int, int, int>, Tune> tune;
   bool autotune = true;
   bool uneven_graphs = true;            // capture and replay uneven-batch group chains
+  int newton_k = -1;                    // FP64 regular iterations: -1 learned, 0 all, n > 0 n
   // uneven batches: pinned staging of the per-request sizes / permutation, capture streams,
   // graph cache and the shapes seen once (captured on their second occurrence)
   int* pin = nullptr;
@@ -401,9 +415,42 @@ struct LaunchTimer {
   }
 };
 
-// Enqueue a whole batched Newton solve: init, max_iter x (Jacobian kernel, LU kernel),
-// final copy-out. Converged requests are skipped by both kernels through the done flags.
-int enqueue_newton(rb_ctx* c, const rb::NewtonF64Args& a, int lu, hipStream_t st) {
+// Iteration history of (set, N) for a batch on stream st, created on first use; nullptr when
+// the stream is being captured (no allocation, no event record) or the resources are missing
+// (the schedule then keeps all max_iter regular iterations).
+NewtonHist* newton_hist(rb_ctx* c, Set* s, int N, hipStream_t st) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
+    return nullptr;
+  NewtonHist& h = s->hist[N];
+  if (!h.ev) {
+    if (dev_alloc(c, h.dev, 256) != RB_OK) return nullptr;
+    if (hipHostMalloc((void**)&h.host, sizeof(int), hipHostMallocDefault) != hipSuccess) {
+      h.host = nullptr;
+      return nullptr;
+    }
+    if (hipEventCreateWithFlags(&h.ev, hipEventDisableTiming) != hipSuccess) {
+      h.ev = nullptr;
+      return nullptr;
+    }
+  }
+  if (h.pending && hipEventQuery(h.ev) == hipSuccess) {
+    h.k = *h.host;
+    h.pending = false;
+  }
+  if (c->newton_k > 0) h.k = c->newton_k;
+  return &h;
+}
+
+// Enqueue a whole batched Newton solve: init, the regular iterations (Jacobian kernel, LU
+// kernel), the tail launch for any further iterations, final copy-out. Converged requests are
+// skipped by every kernel through the done flags. With a history h whose learned count K is
+// below max_iter and the readlane LU, K regular iterations run and the tail takes the rest
+// (the iterates are the same either way); otherwise all max_iter iterations are regular.
+int enqueue_newton(rb_ctx* c, const rb::NewtonF64Args& a_in, int lu, hipStream_t st,
+                   NewtonHist* h = nullptr) {
+  rb::NewtonF64Args a = a_in;
+  a.max_iters = h ? (int*)h->dev.p : nullptr;
   const int NP = a.s.NP;
   const int64_t Bp = a.s.Bp;
   rb::ContractArgs g;
@@ -417,8 +464,12 @@ int enqueue_newton(rb_ctx* c, const rb::NewtonF64Args& a, int lu, hipStream_t st
   g.done = a.s.done;
   g.J = a.s.J; g.mp = a.s.mp;
   g.part = a.s.Wv; g.ldp = NP;
+  int K = a.maxit;
+  if (h && h->k > 0 && h->k < a.maxit &&
+      rb::launch::lu_f64_variant(NP, a.N, lu) == RB_LU_READLANE)
+    K = h->k;
   hipLaunchKernelGGL(rb::newton_init_kernel, dim3(launch_grid(Bp * NP)), dim3(256), 0, st, a);
-  for (int it = 0; it < a.maxit; ++it) {
+  for (int it = 0; it < K; ++it) {
     {
       LaunchTimer t(c, FAM_JACOBIAN, st);
       if (int rc = launch_rc(rb::launch::contract_f64(rb::kModeJac, g, st), "jacobian")) return rc;
@@ -426,9 +477,18 @@ int enqueue_newton(rb_ctx* c, const rb::NewtonF64Args& a, int lu, hipStream_t st
     LaunchTimer t(c, FAM_LU, st);
     if (int rc = launch_rc(rb::launch::lu_f64(NP, a, it, lu, st), "lu")) return rc;
   }
+  if (K < a.maxit) {
+    LaunchTimer t(c, FAM_LU, st);
+    if (int rc = launch_rc(rb::launch::newton_tail_f64(NP, g, a, K, st), "newton tail")) return rc;
+  }
   hipLaunchKernelGGL(rb::newton_final_kernel, dim3(launch_grid((int64_t)a.B * a.ldu)),
                      dim3(256), 0, st, a);
   HIP_TRY(hipGetLastError());
+  if (h) {
+    HIP_TRY(hipMemcpyAsync(h->host, h->dev.p, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipEventRecord(h->ev, st));
+    h->pending = true;
+  }
   return RB_OK;
 }
 
@@ -619,7 +679,7 @@ rb::NewtonF64Args make_args(Set* s, Pack* pk, int N, int B, int ldu, const rb_so
   a.ta = ta; a.tc = tc; a.tf = tf; a.fover = fover; a.u0 = u0; a.nreq = nreq;
   a.F = (const double*)s->F.p;
   a.H = s->hasH ? (const double*)s->H.p : nullptr;
-  a.u = u; a.iters = iters; a.status = status;
+  a.u = u; a.iters = iters; a.status = status; a.max_iters = nullptr;
   const int64_t Bp = ceil_to(B, rb::kTile);
   a.s = carve_state(region, Bp, np_bucket(N), ceil_to((int64_t)N * N, 16), nsplit,
                     needs_f64_j(o.precision));
@@ -627,8 +687,8 @@ rb::NewtonF64Args make_args(Set* s, Pack* pk, int N, int B, int ldu, const rb_so
 }
 
 int enqueue_solve(rb_ctx* c, Set* s, const rb::NewtonF64Args& a, const rb_solve_opts& o,
-                  const Tune& t, char* region, hipStream_t st) {
-  if (o.precision == RB_PREC_F64) return enqueue_newton(c, a, t.lu, st);
+                  const Tune& t, char* region, hipStream_t st, NewtonHist* h = nullptr) {
+  if (o.precision == RB_PREC_F64) return enqueue_newton(c, a, t.lu, st, h);
   char* lp = region + newton_state_bytes(a.s.Bp, a.s.NP, a.s.mp, a.s.nsplit,
                                         needs_f64_j(o.precision));
   return enqueue_newton_lp(c, s, a, o.precision, o.refine_steps, lp, st);
@@ -809,6 +869,7 @@ int rb_create(int device, size_t hbm_budget_bytes, rb_ctx** out) {
   }
   if (const char* v = getenv("RB_AUTOTUNE")) c->autotune = (strcmp(v, "0") != 0);
   if (const char* v = getenv("RB_UNEVEN_GRAPHS")) c->uneven_graphs = (strcmp(v, "0") != 0);
+  if (const char* v = getenv("RB_NEWTON_K")) c->newton_k = atoi(v) < 0 ? -1 : atoi(v);
   *out = c;
   g_err.clear();
   return RB_OK;
@@ -824,6 +885,15 @@ int rb_destroy(rb_ctx* c) {
     for (auto& kv : s.solve_f64) dev_free(c, kv.second.buf);
     for (auto& kv : s.press_f64) dev_free(c, kv.second.buf);
     for (auto& kv : s.solve_lp) dev_free(c, kv.second.buf);
+    for (auto& kv : s.hist) {
+      NewtonHist& h = kv.second;
+      if (h.ev) {
+        (void)hipEventSynchronize(h.ev);
+        (void)hipEventDestroy(h.ev);
+      }
+      if (h.host) (void)hipHostFree(h.host);
+      dev_free(c, h.dev);
+    }
   }
   for (auto& kv : c->ws) dev_free(c, kv.second.buf);
   for (auto& t : c->timed) {
@@ -949,7 +1019,10 @@ int rb_solve_batch(rb_ctx* c, int set, int B, int N, int ldu, const double* ta,
   char* region = (char*)w->buf.p;
   rb::NewtonF64Args a = make_args(s, pk, N, B, ldu, o, ta, tc, tf, fover, u0, u, iters, status,
                                   region, t.nsplit);
-  return enqueue_solve(c, s, a, o, t, region, (hipStream_t)stream);
+  NewtonHist* h = (o.precision == RB_PREC_F64 && c->newton_k != 0)
+                      ? newton_hist(c, s, N, (hipStream_t)stream)
+                      : nullptr;
+  return enqueue_solve(c, s, a, o, t, region, (hipStream_t)stream, h);
 }
 
 int rb_solve_batch_noalloc(rb_ctx* c, int set, int B, int N, int ldu, const double* ta,
