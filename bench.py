@@ -497,7 +497,7 @@ def main():
                        achieved_tflops=work / (ms * 1e-3) / 1e12 if ms > 0 else None)
     names = {"jacobian": ("contract_f64_kernel<kModeJac> (MFMA-F64 Jacobian + A(mu)u)", "mfma",
                           PEAK["fp64_mfma_tflops"]),
-             "lu": ("lu_f64_kernel (FP64 register LU + update)", "alu",
+             "lu": ("lu_f64_kernel (FP64 register LU + update) + newton_tail_f64_kernel", "alu",
                     PEAK["fp64_vector_tflops"]),
              "pressure": ("contract_f64_kernel<kModePressure> + plu_f64_kernel", "mfma",
                           PEAK["fp64_mfma_tflops"])}
