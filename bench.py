@@ -133,7 +133,7 @@ def other_workload(args):
                       FP64-residual refinement step
       uneven_n20_100  B = 16384 with N in {20,...,100} in one call (FP32 + refinement)
       serve_n150      the server under Poisson arrivals, N ~ U{20..150}, FP32 + two refinement
-                      steps, one lane (--serve-prec, --serve-lanes)
+                      steps, three lanes (--serve-prec, --serve-lanes)
     """
     import torch
     from paper_1807_11866_amd import rbns
@@ -392,7 +392,7 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=1.5)
     ap.add_argument("--serve-prec", choices=("f32", "bf16x3", "bf16"), default="f32",
                     help="tensor format of the serve_n150 workload")
-    ap.add_argument("--serve-lanes", type=int, default=1,
+    ap.add_argument("--serve-lanes", type=int, default=3,
                     help="server lanes (batches in flight) of the serve_n150 workload")
     ap.add_argument("--coupled", type=int, default=1,
                     help="time the coupled stabilised (naive) solver against the block method "
@@ -499,7 +499,7 @@ def main():
                           PEAK["fp64_mfma_tflops"]),
              "lu": ("lu_f64_kernel (FP64 register LU + update) + newton_tail_f64_kernel", "alu",
                     PEAK["fp64_vector_tflops"]),
-             "pressure": ("contract_f64_kernel<kModePressure> + plu_f64_kernel", "mfma",
+             "pressure": ("contract_f64_kernel<kModePressure> + pressure solve (plu_mfma_f64_kernel for Np <= 31)", "mfma",
                           PEAK["fp64_mfma_tflops"])}
     for f in kern:
         kern[f]["kernel"], kern[f]["bound"], kern[f]["peak_tflops"] = names[f]

@@ -339,16 +339,18 @@ int rb_assemble_convection(rb_ctx *ctx, int N, int R, int X, int Qc, const doubl
 /*
  * Continuous-batching server on top of one context and tensor set (not part of the paper: a
  * serving form of the online stage). rb_server_submit queues requests (mu, N) and returns at
- * once; a worker thread forms batches from whatever has arrived whenever one of its `lanes`
- * (HIP streams, each with its own device buffers) is free, so requests that arrive while
- * others are on the GPU are admitted as soon as a lane and the HBM budget allow, and the
- * batches of different lanes overlap on the device. A batch is grouped by size class (N
- * rounded up to a multiple of 16, at most the set's N) and each group is solved as one batch
- * of that size (theta(mu) on the device, Newton, optionally the pressure), every request as
- * the leading N x N block of the group's system with its other unknowns held at zero; the
- * tile shapes depend on the group only, so a request's result does not depend on the other
- * requests of its batch (a group's row splits are fixed by its N alone, never by the batch size or
- * the tuning table). rb_server_poll hands back finished
+ * once; a worker thread forms a batch whenever one of its `lanes` (HIP streams, each with its
+ * own device buffers) is free, so requests that arrive while others are on the GPU are
+ * admitted as soon as a lane and the HBM budget allow, and the batches of different lanes
+ * overlap on the device. Requests fall into size classes (N rounded up to a multiple of 16,
+ * at most the set's N); a free lane takes the class of the oldest waiting request, every
+ * queued request of that class up to max_batch, so small bases do not wait for the large ones
+ * and no request waits behind younger ones of its class. A batch is solved as one batch of its
+ * class size (theta(mu) on the device, Newton, optionally the pressure), every request as the
+ * leading N x N block of the class system with its other unknowns held at zero; the tile
+ * shapes depend on the class only, so a request's result does not depend on the other
+ * requests of its batch (a class's row splits are fixed by its N alone, never by the batch
+ * size or the tuning table). rb_server_poll hands back finished
  * results (with the latency from submission to the moment the worker saw the batch finish).
  * The tensor set stays resident; each lane keeps its buffers and workspace between batches.
  * Stop every server of a context before rb_destroy.
@@ -363,10 +365,9 @@ typedef struct {
     int max_iter;             /* Newton iteration limit                                     */
     double tol;               /* Newton tolerance                                           */
     int max_batch;            /* requests per batch (1..65536)                              */
-    int lanes;                /* batches in flight at once (1..4). Each lane uses 7 streams
-                                 (its own + 6 for the size-class groups of its batch); 1 lane
-                                 gives the lowest latency for batches of many size classes,
-                                 several lanes help a single class whose batches are short   */
+    int lanes;                /* batches in flight at once (1..16), each one size class on
+                                 its own stream; lanes beyond the device's hardware queues
+                                 (HIP's default: 4) share queues and wait on each other       */
     size_t hbm_budget_bytes;  /* workspace of the batches in flight (0: no limit): a batch is
                                  cut (halved until it fits) beside the batches in flight, or
                                  waits for them to finish; alone it runs at any size        */

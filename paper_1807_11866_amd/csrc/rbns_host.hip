@@ -1599,17 +1599,12 @@ struct LatHist {
 };
 
 // One lane: a stream, its device buffers for max_batch requests and pinned host mirrors. The
-// size-class groups of a batch run concurrently on the lane's sub-streams (forked from and
-// joined back into the lane stream with events).
-// 6: the lowest latency among 2..12 for batches of 9 size classes (N ~ U{20..150}).
-constexpr int kSubStreams = 6;
-
+// worker admits one size class per batch, so a lane's batch runs in order on its one stream
+// (lanes map one to one onto the device's hardware queues: extra streams per lane would only
+// queue behind other lanes' long kernels).
 struct Lane {
   hipStream_t st = nullptr;
   hipEvent_t done = nullptr;
-  hipStream_t sub[kSubStreams] = {};
-  hipEvent_t fork = nullptr;
-  hipEvent_t join[kSubStreams] = {};
   bool busy = false;
   Clock::time_point t_launch;         // when the batch in flight was launched
   size_t need = 0;                    // workspace estimate of the batch in flight
@@ -1714,26 +1709,17 @@ int launch_batch(rb_server* v, Lane& L) {
   Workspace* w;
   if (int rc = workspace(c, L.st, batch_bytes(v, groups), &w)) return rc;
   char* base = (char*)w->buf.p;
-  HIP_TRY(hipEventRecord(L.fork, L.st));
-  const int nsub = std::min<int>(kSubStreams, (int)groups.size());
-  for (int k = 0; k < nsub; ++k) HIP_TRY(hipStreamWaitEvent(L.sub[k], L.fork, 0));
   double* u = (double*)L.d_u.p;
   double* p = (double*)L.d_p.p;
   int* it = (int*)L.d_int.p;
   int* stt = it + v->cap;
   int* pst = it + 2 * v->cap;
   rb_solve_opts o = {v->o.tol, v->o.max_iter, v->o.precision, v->o.refine_steps};
-  // Groups (largest N first) go to the sub-stream with the least work queued so far
-  // (longest-processing-time-first); a group's time grows about as N^1.5 and, at these small
-  // batch sizes, only weakly with its request count.
-  double load[kSubStreams] = {};
+  // one group per size class (a batch holds one class), in order on the lane's stream
   int r0 = 0;
   for (size_t gi = 0; gi < groups.size(); ++gi) {
     const auto& g = groups[gi];
-    int k = 0;
-    for (int q = 1; q < nsub; ++q) k = load[q] < load[k] ? q : k;
-    load[k] += std::pow((double)g.first, 1.5) * std::sqrt((double)((g.second + 63) / 64));
-    hipStream_t gst = L.sub[k];
+    hipStream_t gst = L.st;
     const int N = g.first, n = g.second;
     const int64_t Bp = ceil_to(n, rb::kTile);
     Pack* pk;
@@ -1755,10 +1741,6 @@ int launch_batch(rb_server* v, Lane& L) {
       base += (size_t)ceil_to((int64_t)pressure_bytes(n, N, Np, serve_press_nsplit(N, Np)), 256);
     }
     r0 += n;
-  }
-  for (int k = 0; k < nsub; ++k) {
-    HIP_TRY(hipEventRecord(L.join[k], L.sub[k]));
-    HIP_TRY(hipStreamWaitEvent(L.st, L.join[k], 0));
   }
   HIP_TRY(hipMemcpyAsync(L.h_u, u, (size_t)B * Nm * sizeof(double), hipMemcpyDeviceToHost, L.st));
   HIP_TRY(hipMemcpyAsync(L.h_int, it, (size_t)3 * v->cap * sizeof(int), hipMemcpyDeviceToHost, L.st));
@@ -1833,18 +1815,34 @@ void serve(rb_server* v) {
       harvest(v, L, q != hipSuccess);
       progress = true;
     }
-    // 2. admit: a free lane takes what has arrived, up to max_batch and the HBM budget
+    // 2. admit: a free lane takes the size class of the oldest waiting request, every
+    //    queued request of that class (in arrival order) up to max_batch and the HBM budget;
+    //    the other classes keep their place for the next free lane
     for (auto& L : v->lanes) {
-      if (L.busy || v->queue.empty()) continue;
-      std::vector<Pending> take;
-      while (!v->queue.empty() && (int)take.size() < v->cap) {
-        Pending q = v->queue.front();
-        v->queue.pop_front();
-        if (q.N < 1 || q.N > v->s->N) { bad_request(v, q); progress = true; continue; }
-        take.push_back(q);
-      }
-      if (take.empty()) continue;
+      if (L.busy) continue;
       const int Nm = v->s->N;
+      while (!v->queue.empty() && (v->queue.front().N < 1 || v->queue.front().N > Nm)) {
+        bad_request(v, v->queue.front());
+        v->queue.pop_front();
+        progress = true;
+      }
+      if (v->queue.empty()) continue;
+      std::vector<Pending> take;
+      {
+        const int cls = serve_group(v->queue.front().N, Nm);
+        std::deque<Pending> rest;
+        for (const Pending& q : v->queue) {
+          if (q.N < 1 || q.N > Nm) {
+            bad_request(v, q);
+            progress = true;
+          } else if ((int)take.size() < v->cap && serve_group(q.N, Nm) == cls) {
+            take.push_back(q);
+          } else {
+            rest.push_back(q);
+          }
+        }
+        v->queue.swap(rest);
+      }
       std::stable_sort(take.begin(), take.end(), [Nm](const Pending& x, const Pending& y) {
         return serve_group(x.N, Nm) > serve_group(y.N, Nm);
       });
@@ -1884,7 +1882,6 @@ void serve(rb_server* v) {
         std::lock_guard<std::mutex> ck(v->c->mu);   // workspaces, packed operands, launches
         rc = launch_batch(v, L);
         if (rc != RB_OK) {
-          for (int k = 0; k < kSubStreams; ++k) (void)hipStreamSynchronize(L.sub[k]);
           (void)hipStreamSynchronize(L.st);
         }
       }
@@ -1916,11 +1913,6 @@ void free_lanes(rb_server* v) {
     for (void* h : {(void*)L.h_mu, (void*)L.h_u, (void*)L.h_p, (void*)L.h_int, (void*)L.h_n})
       if (h) (void)hipHostFree(h);
     if (L.done) (void)hipEventDestroy(L.done);
-    if (L.fork) (void)hipEventDestroy(L.fork);
-    for (int k = 0; k < kSubStreams; ++k) {
-      if (L.join[k]) (void)hipEventDestroy(L.join[k]);
-      if (L.sub[k]) (void)hipStreamDestroy(L.sub[k]);
-    }
     if (L.st) {
       auto it = v->c->ws.find((void*)L.st);
       if (it != v->c->ws.end()) {
@@ -1949,7 +1941,7 @@ int rb_server_start(rb_ctx* c, int set, const rb_server_opts* opts, rb_server** 
   if (o.precision == RB_PREC_F64 && s->N > RB_MAX_N_F64)
     return fail(RB_E_UNSUPPORTED, "rb_server_start: FP64 serving takes set N <= %d",
                 RB_MAX_N_F64);
-  if (o.max_batch < 1 || o.max_batch > 65536 || o.lanes < 1 || o.lanes > 4)
+  if (o.max_batch < 1 || o.max_batch > 65536 || o.lanes < 1 || o.lanes > 16)
     return fail(RB_E_INVAL, "rb_server_start: max_batch=%d lanes=%d", o.max_batch, o.lanes);
   if (o.pressure && s->Np == 0)
     return fail(RB_E_INVAL, "rb_server_start: set %d has no pressure data", set);
@@ -1968,13 +1960,8 @@ int rb_server_start(rb_ctx* c, int set, const rb_server_opts* opts, rb_server** 
     for (auto& L : v->lanes) {
       int rc = RB_OK;
       if (hipStreamCreateWithFlags(&L.st, hipStreamNonBlocking) != hipSuccess ||
-          hipEventCreateWithFlags(&L.done, hipEventDisableTiming) != hipSuccess ||
-          hipEventCreateWithFlags(&L.fork, hipEventDisableTiming) != hipSuccess)
+          hipEventCreateWithFlags(&L.done, hipEventDisableTiming) != hipSuccess)
         rc = fail(RB_E_DEVICE, "rb_server_start: stream/event creation failed");
-      for (int k = 0; k < kSubStreams && !rc; ++k)
-        if (hipStreamCreateWithFlags(&L.sub[k], hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&L.join[k], hipEventDisableTiming) != hipSuccess)
-          rc = fail(RB_E_DEVICE, "rb_server_start: stream/event creation failed");
       if (!rc) rc = dev_alloc(c, L.d_mu, cap * 2 * 8);
       if (!rc) rc = dev_alloc(c, L.d_ta, cap * s->Q * 8);
       if (!rc) rc = dev_alloc(c, L.d_tc, cap * s->Qc * 8);
@@ -2089,8 +2076,6 @@ int rb_server_stop(rb_server* v) {
     std::lock_guard<std::mutex> ck(v->c->mu);
     (void)hipSetDevice(v->c->device);
     for (auto& L : v->lanes) {
-      for (int k = 0; k < kSubStreams; ++k)
-        if (L.sub[k]) (void)hipStreamSynchronize(L.sub[k]);
       if (L.st) (void)hipStreamSynchronize(L.st);
     }
     free_lanes(v);

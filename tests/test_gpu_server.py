@@ -138,5 +138,5 @@ def test_server_bad_size_and_stop_drains(R):
     srv.submit(np.full(100, 0.2), 500.0, 30)
     srv.stop()                                            # drains the queue before returning
     with pytest.raises(R.RbError):
-        R.Server(s, lanes=9)
+        R.Server(s, lanes=17)
     s.close()
