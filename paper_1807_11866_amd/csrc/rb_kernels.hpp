@@ -136,8 +136,8 @@ struct NewtonF64Args {
   double* u;               // [B][ldu]
   int* iters;              // [B]
   int* status;             // [B]
-  int* max_iters;          // largest iteration count of the batch (set by the final kernel), or
-                           // nullptr
+  int* max_iters;          // largest iteration count of the batch (written by the final
+                           // kernel), or nullptr
   NewtonState s;
 };
 
@@ -167,7 +167,6 @@ static __global__ void newton_init_kernel(NewtonF64Args a) {
       a.s.status[b] = 1;
     }
   }
-  if (a.max_iters && blockIdx.x == 0 && threadIdx.x == 0) *a.max_iters = 0;
 }
 
 // ------------------------------------------------------------------ contraction ------
@@ -545,9 +544,9 @@ __global__ __launch_bounds__(kWave * W) void lu_f64_mw_kernel(NewtonF64Args a, i
   }
 }
 
+// (launched with 256-thread blocks)
 static __global__ void newton_final_kernel(NewtonF64Args a) {
   const int NP = a.s.NP;
-  uint32_t most = 0;
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < (int64_t)a.B * a.ldu;
        idx += (int64_t)gridDim.x * blockDim.x) {
     const int64_t b = idx / a.ldu;
@@ -556,12 +555,17 @@ static __global__ void newton_final_kernel(NewtonF64Args a) {
     if (i == 0) {
       a.iters[b] = a.s.iters[b];
       a.status[b] = a.s.status[b];
-      most = max(most, (uint32_t)a.s.iters[b]);
     }
   }
-  if (a.max_iters) {                       // one atomic per wavefront
+  if (a.max_iters && blockIdx.x == 0) {    // the batch's largest count, by block 0 alone
+    __shared__ uint32_t wmax[4];
+    uint32_t most = 0;
+    for (int b = threadIdx.x; b < a.B; b += blockDim.x) most = max(most, (uint32_t)a.s.iters[b]);
     most = wave_max_u32(most);
-    if ((threadIdx.x & 63) == 0 && most > 0) atomicMax(a.max_iters, (int)most);
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = most;
+    __syncthreads();
+    if (threadIdx.x == 0)
+      *a.max_iters = (int)max(max(wmax[0], wmax[1]), max(wmax[2], wmax[3]));
   }
 }
 
