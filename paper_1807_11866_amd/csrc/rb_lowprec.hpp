@@ -173,17 +173,39 @@ void contract_lp_kernel(ContractLpArgs a) {
   constexpr int kP = kS3 ? 2 : 1;           // hi (and lo) parts
   constexpr int kDep = (kS3 && KT <= 14) ? 2 : kDepth;   // k-steps loaded ahead
   opnd wA[kP][kAmax], wT[kP][KT];
+  // hi (and lo) BF16 parts of a float W value by the hardware conversion (round to nearest
+  // even); v - hi is exact in float
+  auto parts = [&](float v, opnd (&dst)[kP], int t) {
+    if constexpr (kBF16) {
+      const uint16_t hi = __builtin_bit_cast(uint16_t, static_cast<__bf16>(v));
+      dst[0][t] = static_cast<short>(hi);
+      if constexpr (kS3) {
+        const float r = v - __uint_as_float(static_cast<uint32_t>(hi) << 16);
+        dst[kP - 1][t] = static_cast<short>(__builtin_bit_cast(uint16_t, static_cast<__bf16>(r)));
+      }
+    }
+  };
   auto make = [&](int ks, opnd (&dst)[kP]) {
     if constexpr (kBF16) {
 #pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        const double v = static_cast<double>(wval(ks * kK + 8 * (lane >> 4) + t));
-        const uint16_t hi = f64_to_bf16(v);
-        dst[0][t] = static_cast<short>(hi);
-        if constexpr (kS3) dst[kP - 1][t] = static_cast<short>(f64_to_bf16(v - bf16_to_f64(hi)));
-      }
+      for (int t = 0; t < 8; ++t) parts(wval(ks * kK + 8 * (lane >> 4) + t), dst, t);
     } else {
       dst[0] = wval(ks * kK + (lane >> 4));
+    }
+  };
+  // BF16 tensor k-step ks: rows t = 32 ks + 8 (lane/16) + e, e = 0..7, walked as (q, l) with
+  // t = q N + l instead of one division per value
+  auto make_t = [&](int ks, opnd (&dst)[kP]) {
+    int l = kK * ks + 8 * (lane >> 4), q = 0;
+    while (l >= N && q < kMaxQc) { l -= N; ++q; }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      float tq = 0.f;
+#pragma unroll
+      for (int qq = 0; qq < kMaxQc; ++qq) tq = (q == qq) ? tcv[qq] : tq;
+      parts(q < kMaxQc ? tq * ul[bl * N + l] : 0.f, dst, e);
+      if (++l == N) { l = 0; ++q; }
+      if (q >= kMaxQc) l = 0;
     }
   };
 #pragma unroll
@@ -196,7 +218,8 @@ void contract_lp_kernel(ContractLpArgs a) {
 #pragma unroll
   for (int ks = 0; ks < KT; ++ks) {
     opnd tmp[kP];
-    make(a.kA + ks, tmp);
+    if constexpr (kBF16) make_t(ks, tmp);
+    else make(a.kA + ks, tmp);
 #pragma unroll
     for (int pp = 0; pp < kP; ++pp) wT[pp][ks] = tmp[pp];
   }
