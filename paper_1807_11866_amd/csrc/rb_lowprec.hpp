@@ -120,8 +120,9 @@ __host__ __device__ inline int64_t contract_lp_lds_bytes(int N) {
 // one chunk. kS3 (BF16x3): operand and W are both split into hi + lo BF16 parts and every
 // product is hi*hi + hi*lo + lo*hi (three MFMAs, about 16 mantissa bits). Accumulator layout
 // of the 16x16 FP32 MFMAs: lane l, element v = row 4*(l/16) + v, column l%16.
-// BF16x3 with KT <= 14 runs two waves per SIMD (hi + lo W in registers leave room for a
-// two-k-step prefetch only); measured 26 % faster than one wave with a six-step prefetch.
+// BF16x3 with KT <= 14 runs two waves per SIMD with a four-k-step prefetch (hi + lo W in
+// registers, two BF16 values per register); two and six steps measured slower, and one wave
+// per SIMD with a six-step prefetch 26 % slower.
 template <bool kBF16, int KT, bool kS3 = false>
 __global__ __launch_bounds__(kThreads)
 __attribute__((amdgpu_waves_per_eu(kS3 && KT <= 14 ? 2 : 1)))
@@ -171,24 +172,35 @@ void contract_lp_kernel(ContractLpArgs a) {
     return q < kMaxQc ? tq * ul[bl * N + l] : 0.f;
   };
   constexpr int kP = kS3 ? 2 : 1;           // hi (and lo) parts
-  constexpr int kDep = (kS3 && KT <= 14) ? 2 : kDepth;   // k-steps loaded ahead
+  constexpr int kDep = (kS3 && KT <= 14) ? 4 : kDepth;   // k-steps loaded ahead
   opnd wA[kP][kAmax], wT[kP][KT];
-  // hi (and lo) BF16 parts of a float W value by the hardware conversion (round to nearest
-  // even); v - hi is exact in float
-  auto parts = [&](float v, opnd (&dst)[kP], int t) {
+  // hi (and lo) BF16 parts of the eight float W values of a k-step, two per register by the
+  // hardware conversion (round to nearest even); v - hi is exact in float
+  auto parts = [&](const float (&v)[8], opnd (&dst)[kP]) {
     if constexpr (kBF16) {
-      const uint16_t hi = __builtin_bit_cast(uint16_t, static_cast<__bf16>(v));
-      dst[0][t] = static_cast<short>(hi);
-      if constexpr (kS3) {
-        const float r = v - __uint_as_float(static_cast<uint32_t>(hi) << 16);
-        dst[kP - 1][t] = static_cast<short>(__builtin_bit_cast(uint16_t, static_cast<__bf16>(r)));
+      typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+      typedef float f32x2 __attribute__((ext_vector_type(2)));
+      typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+      u32x4 h, l;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        h[i] = __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){v[2 * i], v[2 * i + 1]}, bf16x2));
+        if constexpr (kS3) {
+          const float r0 = v[2 * i] - __uint_as_float(h[i] << 16);
+          const float r1 = v[2 * i + 1] - __uint_as_float(h[i] & 0xffff0000u);
+          l[i] = __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){r0, r1}, bf16x2));
+        }
       }
+      dst[0] = __builtin_bit_cast(opnd, h);
+      if constexpr (kS3) dst[kP - 1] = __builtin_bit_cast(opnd, l);
     }
   };
   auto make = [&](int ks, opnd (&dst)[kP]) {
     if constexpr (kBF16) {
+      float v[8];
 #pragma unroll
-      for (int t = 0; t < 8; ++t) parts(wval(ks * kK + 8 * (lane >> 4) + t), dst, t);
+      for (int t = 0; t < 8; ++t) v[t] = wval(ks * kK + 8 * (lane >> 4) + t);
+      parts(v, dst);
     } else {
       dst[0] = wval(ks * kK + (lane >> 4));
     }
@@ -198,15 +210,17 @@ void contract_lp_kernel(ContractLpArgs a) {
   auto make_t = [&](int ks, opnd (&dst)[kP]) {
     int l = kK * ks + 8 * (lane >> 4), q = 0;
     while (l >= N && q < kMaxQc) { l -= N; ++q; }
+    float v[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       float tq = 0.f;
 #pragma unroll
       for (int qq = 0; qq < kMaxQc; ++qq) tq = (q == qq) ? tcv[qq] : tq;
-      parts(q < kMaxQc ? tq * ul[bl * N + l] : 0.f, dst, e);
+      v[e] = q < kMaxQc ? tq * ul[bl * N + l] : 0.f;
       if (++l == N) { l = 0; ++q; }
       if (q >= kMaxQc) l = 0;
     }
+    parts(v, dst);
   };
 #pragma unroll
   for (int ks = 0; ks < kAmax; ++ks) {
