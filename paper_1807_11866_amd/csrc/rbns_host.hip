@@ -1572,6 +1572,16 @@ struct Pending {
   Clock::time_point t_submit;
 };
 
+// Waiting requests, one FIFO per size class (key: the class size) plus the requests with an
+// invalid N; the oldest waiting request is the smallest ticket among the class fronts, so
+// taking a class costs the batch it takes, whatever the length of the queue.
+struct WaitQueue {
+  std::map<int, std::deque<Pending>> cls;
+  std::deque<Pending> bad;
+  size_t n = 0;                       // requests in cls
+  bool empty() const { return n == 0 && bad.empty(); }
+};
+
 // Latency quantiles in bounded memory: log-spaced bins of ratio 1.01 from 1 us to 1000 s
 // (2083 bins), so a quantile is known to within 0.5 %, whatever the number of requests.
 struct LatHist {
@@ -1629,7 +1639,7 @@ struct rb_server {
   std::thread worker;
   std::mutex qm;                      // queue, results, stats
   std::condition_variable qcv;
-  std::deque<Pending> queue;
+  WaitQueue queue;
   std::deque<rb_result> results;
   bool stopping = false;
   long long next_ticket = 1, submitted = 0, completed = 0, batches = 0;
@@ -1821,31 +1831,21 @@ void serve(rb_server* v) {
     for (auto& L : v->lanes) {
       if (L.busy) continue;
       const int Nm = v->s->N;
-      while (!v->queue.empty() && (v->queue.front().N < 1 || v->queue.front().N > Nm)) {
-        bad_request(v, v->queue.front());
-        v->queue.pop_front();
-        progress = true;
-      }
-      if (v->queue.empty()) continue;
+      WaitQueue& wq = v->queue;
+      for (const Pending& q : wq.bad) bad_request(v, q);
+      progress = progress || !wq.bad.empty();
+      wq.bad.clear();
+      if (wq.n == 0) continue;
+      std::deque<Pending>* oldest = nullptr;
+      for (auto& kv : wq.cls)
+        if (!kv.second.empty() && (!oldest || kv.second.front().ticket < oldest->front().ticket))
+          oldest = &kv.second;
       std::vector<Pending> take;
-      {
-        const int cls = serve_group(v->queue.front().N, Nm);
-        std::deque<Pending> rest;
-        for (const Pending& q : v->queue) {
-          if (q.N < 1 || q.N > Nm) {
-            bad_request(v, q);
-            progress = true;
-          } else if ((int)take.size() < v->cap && serve_group(q.N, Nm) == cls) {
-            take.push_back(q);
-          } else {
-            rest.push_back(q);
-          }
-        }
-        v->queue.swap(rest);
+      while (!oldest->empty() && (int)take.size() < v->cap) {
+        take.push_back(oldest->front());
+        oldest->pop_front();
       }
-      std::stable_sort(take.begin(), take.end(), [Nm](const Pending& x, const Pending& y) {
-        return serve_group(x.N, Nm) > serve_group(y.N, Nm);
-      });
+      wq.n -= take.size();
       auto groups_of = [Nm](const std::vector<Pending>& t, size_t n) {
         std::vector<std::pair<int, int>> g;
         for (size_t i = 0; i < n; ++i) {
@@ -1863,10 +1863,10 @@ void serve(rb_server* v) {
         need = batch_bytes(v, groups_of(take, n));
       }
       if (budget && v->inflight + need > budget && v->inflight > 0) n = 0;   // wait for room
-      for (size_t i = take.size(); i-- > n;) v->queue.push_front(take[i]);
+      for (size_t i = take.size(); i-- > n;) oldest->push_front(take[i]);
+      wq.n += take.size() - n;
       if (n == 0) continue;
       take.resize(n);
-      // keep the N order of the (possibly cut) batch: rows grouped by N
       L.batch = std::move(take);
       L.need = need;
       L.busy = true;
@@ -2023,7 +2023,12 @@ int rb_server_submit(rb_server* v, const rb_request* reqs, int n, long long* tic
       q.alpha = reqs[i].alpha;
       q.re = reqs[i].re;
       q.t_submit = now;
-      v->queue.push_back(q);
+      if (q.N < 1 || q.N > v->s->N) {
+        v->queue.bad.push_back(q);
+      } else {
+        v->queue.cls[serve_group(q.N, v->s->N)].push_back(q);
+        ++v->queue.n;
+      }
       if (tickets) tickets[i] = q.ticket;
     }
     v->submitted += n;
