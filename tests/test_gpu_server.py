@@ -140,3 +140,33 @@ def test_server_bad_size_and_stop_drains(R):
     with pytest.raises(R.RbError):
         R.Server(s, lanes=17)
     s.close()
+
+
+def test_server_burst_batches_by_class(R, oracle_lib):
+    """A burst of 10000 requests in four size classes (N = 10, 25, 40, 50: classes 16, 32,
+    48, 50), queued in one submission and served by one lane with max_batch 1000: every batch
+    holds one class, so the server runs sum over classes of ceil(n_c / 1000) = 12 batches
+    (ten if batches mixed classes), every request converges, and a sample agrees with the
+    oracle at its own N."""
+    O = oracle_lib
+    cfg = get_config("batched_n50")
+    ts = make_tensor_set(cfg)
+    s = R.Solver(ts)
+    rng = np.random.default_rng(5)
+    n = 10000
+    Ns = np.repeat(np.array([10, 25, 40, 50]), n // 4)
+    rng.shuffle(Ns)
+    mu = draw_mu(cfg, n, seed_offset=9)
+    srv = R.Server(s, max_batch=1000, lanes=1)
+    try:
+        t = srv.submit(mu[:, 0], mu[:, 1], Ns)
+        got = _collect(srv, n, timeout=120.0)
+        assert all(got[k]["status"] == 0 for k in t)
+        assert srv.stats()["batches"] == 12
+        pick = rng.choice(n, 8, replace=False)
+        r = O.solve_batch(O.OracleSet(ts), mu[pick], Nreq=Ns[pick])
+        for m, i in enumerate(pick):
+            assert _rel(got[t[i]]["u"], r["u"][m, :Ns[i]]) <= 1e-10, i
+    finally:
+        srv.stop()
+        s.close()
