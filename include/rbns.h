@@ -423,7 +423,9 @@ int rb_server_stop(rb_server *srv);
  */
 int rb_timing_enable(rb_ctx *ctx, int enable);
 /* (family "residual": the FP64 residual contraction of the mixed-precision refinement;
- *  family "reconstruct": rb_reconstruct_pressure) */
+ *  family "reconstruct": rb_reconstruct_pressure; family "stokes": the first Jacobian of a
+ *  solve without initial iterates, A(mu) assembled from the affine operators, at every
+ *  precision) */
 int rb_timing_read(rb_ctx *ctx, const char *family, double *total_ms, int *launches);
 
 #ifdef __cplusplus

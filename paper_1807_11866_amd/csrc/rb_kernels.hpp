@@ -141,6 +141,56 @@ struct NewtonF64Args {
   NewtonState s;
 };
 
+// First Newton step from u = 0 (no initial iterates given): the convection terms of the
+// Jacobian J(u) = A(mu) + C(., u) + C(u, .) vanish (Section 3.5), so J = sum_q theta^a_q A_q
+// is assembled from the Q affine operators alone instead of by the contraction over the
+// whole tensor, and the partial sums of A(mu) u are zero; the step is the Stokes solve.
+// The operators are read from the affine k-steps of the packed operand, where row m = j N + i
+// of A_q sits at ((m/16) nks + q/4) 64 + (q%4) 16 + m%16 (16 consecutive rows per 128 bytes),
+// and J is stored as the contraction stores it (J[b][m] = A(mu)[i][j]). Workgroup (x, y) takes
+// requests 16x .. 16x + 15 and rows 256y .. 256y + 255: each thread reads its row of A_q once
+// per q for 16 requests (theta^a uniform across the workgroup), the stores of a request are
+// contiguous. Sums run over q in order from zero, so every request gets the same J.
+constexpr int kStokesReq = 16;
+
+template <typename T>
+__device__ __forceinline__ void stokes_tile(const NewtonF64Args& a, T* J, int64_t mp, T* part,
+                                            int64_t npart) {
+  const int NN = a.N * a.N, Q = a.Q;
+  const int m = blockIdx.y * 256 + threadIdx.x;
+  const int64_t b0 = (int64_t)blockIdx.x * kStokesReq;
+  if (m < NN) {
+    const double* op = a.op + (int64_t)(m >> 4) * a.nks * 64 + (m & 15);
+    double acc[kStokesReq];
+#pragma unroll
+    for (int r = 0; r < kStokesReq; ++r) acc[r] = 0.0;
+    for (int q = 0; q < Q; ++q) {
+      const double x = op[(q >> 2) * 64 + ((q & 3) << 4)];
+#pragma unroll
+      for (int r = 0; r < kStokesReq; ++r) {
+        const int64_t b = b0 + r < a.B ? b0 + r : a.B - 1;
+        acc[r] = fma(a.ta[b * Q + q], x, acc[r]);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < kStokesReq; ++r)
+      if (b0 + r < a.B) J[(b0 + r) * mp + m] = static_cast<T>(acc[r]);
+  }
+  // zero partial sums of A(mu) u
+  const int64_t nthr = (int64_t)gridDim.x * gridDim.y * blockDim.x;
+  for (int64_t idx = ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * blockDim.x + threadIdx.x;
+       idx < npart; idx += nthr)
+    part[idx] = T(0);
+}
+
+__host__ inline dim3 stokes_grid(int B, int N) {
+  return dim3((unsigned)((B + kStokesReq - 1) / kStokesReq), (unsigned)((N * N + 255) / 256));
+}
+
+static __global__ __launch_bounds__(256) void stokes_jacobian_kernel(NewtonF64Args a) {
+  stokes_tile<double>(a, a.s.J, a.s.mp, a.s.Wv, (int64_t)a.s.nsplit * a.s.Bp * a.s.NP);
+}
+
 // Start of a batch solve: iterates from u0 (or 0), f(mu) (or the override), flags.
 static __global__ void newton_init_kernel(NewtonF64Args a) {
   const int64_t Bp = a.s.Bp;

@@ -345,6 +345,16 @@ void contract_lp_kernel(ContractLpArgs a) {
   }
 }
 
+// First low-precision Newton step from u = 0 (as stokes_jacobian_kernel): J32 = A(mu),
+// summed in FP64 from the packed FP64 operand and rounded once, and zero partial sums of
+// A(mu) u.
+static __global__ __launch_bounds__(256) void stokes_jacobian_lp_kernel(NewtonF64Args a,
+                                                                      float* J32, int64_t mp,
+                                                                      float* part32,
+                                                                      int nsplit) {
+  stokes_tile<float>(a, J32, mp, part32, (int64_t)nsplit * a.s.Bp * a.s.NP);
+}
+
 // Status of a request whose refinement steps ran out while each refinement update after the
 // first was at most half the update before it (the refinement still contracting): its error is
 // of the order of the last update times that contraction. RB_ST_MAXIT then marks stagnation or

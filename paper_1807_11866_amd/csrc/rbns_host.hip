@@ -379,9 +379,9 @@ size_t solve_bytes(const Set* s, int N, int64_t Bp, int nsplit, int precision) {
 }
 
 enum { FAM_JACOBIAN = 0, FAM_LU = 1, FAM_PRESSURE = 2, FAM_RESIDUAL = 3, FAM_RECONSTRUCT = 4,
-       FAM_COUNT = 5 };
+       FAM_STOKES = 5, FAM_COUNT = 6 };
 const char* const kFamilies[FAM_COUNT] = {"jacobian", "lu", "pressure", "residual",
-                                          "reconstruct"};
+                                          "reconstruct", "stokes"};
 
 hipEvent_t take_event(rb_ctx* c) {
   if (!c->event_pool.empty()) {
@@ -443,10 +443,12 @@ NewtonHist* newton_hist(rb_ctx* c, Set* s, int N, hipStream_t st) {
 }
 
 // Enqueue a whole batched Newton solve: init, the regular iterations (Jacobian kernel, LU
-// kernel), the tail launch for any further iterations, final copy-out. Converged requests are
-// skipped by every kernel through the done flags. With a history h whose learned count K is
-// below max_iter and the readlane LU, K regular iterations run and the tail takes the rest
-// (the iterates are the same either way); otherwise all max_iter iterations are regular.
+// kernel; without initial iterates the first Jacobian is A(mu), assembled from the affine
+// operators alone), the tail launch for any further iterations, final copy-out. Converged
+// requests are skipped by every kernel through the done flags. With a history h whose
+// learned count K is below max_iter and the readlane LU, K regular iterations run and the
+// tail takes the rest (the iterates are the same either way); otherwise all max_iter
+// iterations are regular.
 int enqueue_newton(rb_ctx* c, const rb::NewtonF64Args& a_in, int lu, hipStream_t st,
                    NewtonHist* h = nullptr) {
   rb::NewtonF64Args a = a_in;
@@ -470,7 +472,12 @@ int enqueue_newton(rb_ctx* c, const rb::NewtonF64Args& a_in, int lu, hipStream_t
     K = h->k;
   hipLaunchKernelGGL(rb::newton_init_kernel, dim3(launch_grid(Bp * NP)), dim3(256), 0, st, a);
   for (int it = 0; it < K; ++it) {
-    {
+    if (it == 0 && !a.u0) {                // from u = 0: J = A(mu), A(mu) u = 0
+      LaunchTimer t(c, FAM_STOKES, st);
+      hipLaunchKernelGGL(rb::stokes_jacobian_kernel, rb::stokes_grid(a.B, a.N), dim3(256), 0,
+                         st, a);
+      HIP_TRY(hipGetLastError());
+    } else {
       LaunchTimer t(c, FAM_JACOBIAN, st);
       if (int rc = launch_rc(rb::launch::contract_f64(rb::kModeJac, g, st), "jacobian")) return rc;
     }
@@ -539,7 +546,12 @@ int enqueue_newton_lp(rb_ctx* c, Set* s, const rb::NewtonF64Args& a, int prec, i
 
   hipLaunchKernelGGL(rb::newton_init_kernel, dim3(launch_grid(Bp * NP)), dim3(256), 0, st, a);
   for (int it = 0; it < a.maxit; ++it) {
-    {
+    if (it == 0 && !a.u0) {                // from u = 0: J = A(mu), A(mu) u = 0
+      LaunchTimer t(c, FAM_STOKES, st);
+      hipLaunchKernelGGL(rb::stokes_jacobian_lp_kernel, rb::stokes_grid(a.B, N), dim3(256), 0,
+                         st, a, J32, mp, part32, nsplit);
+      HIP_TRY(hipGetLastError());
+    } else {
       LaunchTimer t(c, FAM_JACOBIAN, st);
       if (int rc = launch_rc(rb::launch::contract_lp(prec, KT, gl, st), "lp jacobian")) return rc;
     }
