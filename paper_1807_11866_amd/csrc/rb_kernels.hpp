@@ -137,7 +137,7 @@ struct NewtonF64Args {
   int* iters;              // [B]
   int* status;             // [B]
   int* max_iters;          // largest iteration count of the batch (written by the final
-                           // kernel), or nullptr
+                           // kernel into pinned host memory), or nullptr
   NewtonState s;
 };
 
@@ -614,8 +614,10 @@ static __global__ void newton_final_kernel(NewtonF64Args a) {
     most = wave_max_u32(most);
     if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = most;
     __syncthreads();
-    if (threadIdx.x == 0)
+    if (threadIdx.x == 0) {                // pinned host word: made visible system-wide
       *a.max_iters = (int)max(max(wmax[0], wmax[1]), max(wmax[2], wmax[3]));
+      __threadfence_system();
+    }
   }
 }
 

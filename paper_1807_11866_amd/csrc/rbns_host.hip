@@ -68,12 +68,11 @@ struct Pack {              // packed MFMA operand for one basis size
   int naff = 0;            // long expansions: affine chunks of the same length (nks_s of them)
 };
 
-// Newton iteration counts of the FP64 batches of one basis size: the final kernel leaves the
-// batch's largest count in `dev`, which is copied to `host` behind `ev`; a later batch reads it
-// once the copy has landed (never waiting for it) and runs that many regular iterations before
-// the tail launch.
+// Newton iteration counts of the FP64 batches of one basis size: the final kernel writes the
+// batch's largest count straight into the pinned `host` word, and `ev` is recorded behind it;
+// a later batch reads the word once the event has completed (never waiting for it) and runs
+// that many regular iterations before the tail launch.
 struct NewtonHist {
-  DevBuf dev;
   int* host = nullptr;
   hipEvent_t ev = nullptr;
   bool pending = false;
@@ -424,7 +423,6 @@ NewtonHist* newton_hist(rb_ctx* c, Set* s, int N, hipStream_t st) {
     return nullptr;
   NewtonHist& h = s->hist[N];
   if (!h.ev) {
-    if (dev_alloc(c, h.dev, 256) != RB_OK) return nullptr;
     if (hipHostMalloc((void**)&h.host, sizeof(int), hipHostMallocDefault) != hipSuccess) {
       h.host = nullptr;
       return nullptr;
@@ -452,7 +450,7 @@ NewtonHist* newton_hist(rb_ctx* c, Set* s, int N, hipStream_t st) {
 int enqueue_newton(rb_ctx* c, const rb::NewtonF64Args& a_in, int lu, hipStream_t st,
                    NewtonHist* h = nullptr) {
   rb::NewtonF64Args a = a_in;
-  a.max_iters = h ? (int*)h->dev.p : nullptr;
+  a.max_iters = h ? h->host : nullptr;
   const int NP = a.s.NP;
   const int64_t Bp = a.s.Bp;
   rb::ContractArgs g;
@@ -492,7 +490,6 @@ int enqueue_newton(rb_ctx* c, const rb::NewtonF64Args& a_in, int lu, hipStream_t
                      dim3(256), 0, st, a);
   HIP_TRY(hipGetLastError());
   if (h) {
-    HIP_TRY(hipMemcpyAsync(h->host, h->dev.p, sizeof(int), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipEventRecord(h->ev, st));
     h->pending = true;
   }
@@ -904,7 +901,6 @@ int rb_destroy(rb_ctx* c) {
         (void)hipEventDestroy(h.ev);
       }
       if (h.host) (void)hipHostFree(h.host);
-      dev_free(c, h.dev);
     }
   }
   for (auto& kv : c->ws) dev_free(c, kv.second.buf);

@@ -218,6 +218,37 @@ def test_stokes_limit_on_gpu(R, c2):
     s.close()
 
 
+@pytest.mark.parametrize("N,Q,prec,tol", [
+    (37, 3, "F64", 1e-12), (50, 14, "F64", 1e-12), (64, 50, "F64", 1e-12),
+    (37, 3, "F32", 1e-5), (50, 12, "F32", 1e-5), (37, 3, "BF16X3", 1e-5),
+    (64, 12, "BF16X3", 1e-5)])
+def test_first_step_is_the_stokes_solve(R, N, Q, prec, tol):
+    """One Newton step from u = 0 solves A(mu) u = f(mu) (the convection terms of the
+    Jacobian vanish there), whatever theta^c. The affine operators are made non-symmetric so
+    that a transposed assembly of A(mu) fails; Q = 3 sits in the FP64 contraction's affine
+    prefix, Q = 14 and 50 in affine chunks of their own (the mixed precisions take Q <= 12);
+    N*N not a multiple of 16 and a ragged batch of 300 leave partial row blocks and request
+    groups."""
+    rng = np.random.default_rng(N + Q)
+    ts = _random_set(N, Q=Q, seed=N, scale=0.1)
+    ts.A = ts.A + 0.3 * rng.standard_normal((Q, N, N)) / np.sqrt(N)
+    B = 300
+    ta = rng.uniform(0.1, 1.0, (B, Q))
+    tc = rng.uniform(-1.0, 1.0, (B, ts.Qc))
+    tf = rng.standard_normal((B, ts.Qf))
+    s = R.Solver(ts)
+    th = dict(ta=_dev(ta), tc=_dev(tc), tf=_dev(tf))
+    print(f"[first step] N={N} Q={Q} {prec}", flush=True)
+    out = s.solve(th, max_iter=1, precision=getattr(R, "RB_PREC_" + prec), refine_steps=0)
+    torch.cuda.synchronize()
+    u = out["u"].cpu().numpy()
+    ref = np.stack([np.linalg.solve(np.tensordot(ta[b], ts.A, 1), tf[b] @ ts.F)
+                    for b in range(B)])
+    assert np.max(_rel(u, ref)) <= tol
+    assert np.all(out["iters"].cpu().numpy() == 1)
+    s.close()
+
+
 # ------------------------------------------------------------- mixed precision ----
 # Low-precision Newton (FP32, BF16 or BF16 hi/lo tensors on MFMA, FP32 LU, FP64 iterates)
 # followed by refinement steps with the FP64 residual: the result must reach the FP64 oracle
