@@ -530,7 +530,8 @@ def main():
             kernel="stokes_jacobian_kernel (first Jacobian A(mu) from the affine operators)",
             bound="hbm", total_ms=stokes_ms, launches=stokes_n, avg_launch_ms=stokes_ms / stokes_n,
             achieved_gbs=sb / (stokes_ms * 1e-3) / 1e9, peak_gbs=PEAK["hbm_gbs"],
-            frac=sb / (stokes_ms * 1e-3) / 1e9 / PEAK["hbm_gbs"])
+            frac=sb / (stokes_ms * 1e-3) / 1e9 / PEAK["hbm_gbs"],
+            traffic=recorded_traffic("stokes"))
 
     # ---- parity of the timed outputs against the oracle on a sample ------------------------
     extra = {}
