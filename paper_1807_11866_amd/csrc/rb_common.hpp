@@ -144,8 +144,7 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
 template <int NP, bool kLdsBcast, typename T>
 __device__ __forceinline__ int lu_solve_rows(T (&a)[NP], T rhs, int lane, T* prow, T& x) {
   int pos = lane;
-  bool singular = false;
-  T mypiv = T(1);
+  T mypiv = T(1);                          // this row's pivot, once it has been the pivot row
   // Pivot search of column k over the rows at positions >= k: the wavefront maximum of the
   // key, the first lane holding it (`tied`: every lane holding it), and, assuming that lane
   // is the pivot, the pivot value and this row's multiplier. Branch-free, so that the search
@@ -181,14 +180,13 @@ __device__ __forceinline__ int lu_solve_rows(T (&a)[NP], T rhs, int lane, T* pro
       piv = bcast(a[k], pv);
       l = lane == pv ? T(0) : a[k] / (piv == T(0) ? T(1) : piv);
     }
-    singular |= (piv == T(0));
     const int pk = pv;
     const T lk = l;
     const int ppos = bcast(pos, pk);
     const bool me = lane == pk;
     pos = (pos == k) ? ppos : pos;
     pos = me ? k : pos;
-    mypiv = me ? (piv == T(0) ? T(1) : piv) : mypiv;
+    mypiv = me ? piv : mypiv;
     if (kLdsBcast) {
       if (me) {
 #pragma unroll
@@ -226,11 +224,14 @@ __device__ __forceinline__ int lu_solve_rows(T (&a)[NP], T rhs, int lane, T* pro
     rhs = fma(-lk, kLdsBcast ? prow[NP] : bcast(rhs, pk), rhs);
     if (kLdsBcast) wave_lds_order();
   }
-  if (lane < NP) prow[pos] = rhs / mypiv;
+  // Every row is the pivot row of exactly one step, so a zero pivot shows in its row's mypiv
+  // (tested here rather than per step, which would keep every step's pivot live).
+  const bool zero = lane < NP && mypiv == T(0);
+  if (lane < NP) prow[pos] = rhs / (zero ? T(1) : mypiv);
   wave_lds_order();
   x = lane < NP ? prow[lane] : T(0);
   wave_lds_order();
-  return singular ? 2 : 0;
+  return __any(zero) ? 2 : 0;
 }
 
 }  // namespace rb
@@ -269,8 +270,7 @@ __device__ __forceinline__ int gj_solve_mw(T (&a)[NP], T rhs, int row, int lane,
   constexpr int kVec = GjShared<NP, W, T>::kVec;
   typedef T vec_t __attribute__((ext_vector_type(kVec)));
   int pos = row;
-  bool singular = false;
-  T mypiv = T(1);
+  T mypiv = T(1);                          // this row's pivot, once it has been the pivot row
 #pragma unroll
   for (int k = 0; k < NP; ++k) {
     const int buf = k & 1;
@@ -322,14 +322,12 @@ __device__ __forceinline__ int gj_solve_mw(T (&a)[NP], T rhs, int row, int lane,
       bp = take ? p2 : bp;
     }
     const T* pr = &sh.rows[buf][ws][0];
-    T piv = pr[k];
-    singular |= (piv == T(0));
-    piv = (piv == T(0)) ? T(1) : piv;
+    const T piv = pr[k];
     const bool me = (wv == ws) && (lane == pl);
     pos = (pos == k) ? bp : pos;
     pos = me ? k : pos;
     mypiv = me ? piv : mypiv;
-    const T l = me ? T(0) : a[k] / piv;
+    const T l = me ? T(0) : a[k] / (piv == T(0) ? T(1) : piv);
 #pragma unroll
     for (int j0 = (k + 1) & ~(kVec - 1); j0 < kRow; j0 += 2 * kVec) {
       vec_t pj[2];
@@ -345,12 +343,23 @@ __device__ __forceinline__ int gj_solve_mw(T (&a)[NP], T rhs, int row, int lane,
           else if (j == NP) rhs = fma(-l, pj[h2][t], rhs);
         }
       }
+      // pin the chunk's updates here: otherwise they sink to their next use, past the next
+      // step's pivot search, and every value read from the pivot row stays live until then
+      // (beyond 104 unknowns the pins make the compile take tens of minutes, so not there)
+      if constexpr (NP <= 104) {
+#pragma unroll
+        for (int j = j0; j < j0 + 2 * kVec; ++j) {
+          if (j > k && j < NP) asm volatile("" : "+v"(a[j]));
+          else if (j == NP) asm volatile("" : "+v"(rhs));
+        }
+      }
       __builtin_amdgcn_sched_barrier(0);
     }
   }
-  if (row < NP) sh.xs[pos] = rhs / mypiv;
-  __syncthreads();
-  return singular ? 2 : 0;
+  // a zero pivot shows in its row's mypiv (every row is the pivot row of exactly one step)
+  const bool zero = row < NP && mypiv == T(0);
+  if (row < NP) sh.xs[pos] = rhs / (zero ? T(1) : mypiv);
+  return __syncthreads_or(zero) ? 2 : 0;
 }
 
 // Sum of a per-thread double over the workgroup (W wavefronts), two values at once.
