@@ -41,6 +41,8 @@ int lu_f64_mfma(const NewtonF64Args& a, int it, hipStream_t st);
 int plu_f64_mfma(const PressureF64Args& a, hipStream_t st);
 int lu_lp_mw(int NP, bool refine, const LpNewtonArgs& a, int it, hipStream_t st);
 int lu_lp_mw_wide(int NP, bool refine, const LpNewtonArgs& a, int it, hipStream_t st);
+int lu_lp_mw_wide2(int NP, bool refine, const LpNewtonArgs& a, int it, hipStream_t st);
+int lu_lp_mw_wide3(int NP, bool refine, const LpNewtonArgs& a, int it, hipStream_t st);
 int contract_lp_f32_wide(int KT, const ContractLpArgs& g, hipStream_t st);
 int contract_lp_bf16x3(int KT, const ContractLpArgs& g, hipStream_t st);
 

@@ -1,17 +1,11 @@
-// Instantiations of the multi-wavefront (Gauss-Jordan) LU kernels for NP > 64: FP64 Newton
-// NP = 72..96, FP32 mixed-precision NP = 72..104 (multiples of 8; larger FP32 systems:
-// rb_launch_lu_mw_wide.hip); W = ceil(NP/64) wavefronts per system.
+// Instantiations of the multi-wavefront (Gauss-Jordan) FP32 mixed-precision LU kernel for
+// NP = 72..104 (multiples of 8; larger systems: rb_launch_lu_mw_wide*.hip, FP64 Newton
+// systems: rb_launch_lu_mw_f64.hip); W = ceil(NP/64) wavefronts per system. The sizes are
+// spread over several translation units so that they compile in parallel.
 #include "rb_launch.hpp"
 
 namespace rb {
 namespace launch {
-
-template <int NP>
-static int go_f64(const NewtonF64Args& a, int it, hipStream_t st) {
-  constexpr int W = (NP + kWave - 1) / kWave;
-  hipLaunchKernelGGL((lu_f64_mw_kernel<NP, W>), dim3(a.B), dim3(kWave * W), 0, st, a, it);
-  return hipGetLastError() == hipSuccess ? 0 : -3;
-}
 
 template <int NP>
 static int go_lp(bool refine, const LpNewtonArgs& a, int it, hipStream_t st) {
@@ -19,15 +13,6 @@ static int go_lp(bool refine, const LpNewtonArgs& a, int it, hipStream_t st) {
   hipLaunchKernelGGL((lu_lp_mw_kernel<NP, W>), dim3(a.B), dim3(kWave * W), 0, st, a, it,
                      refine ? 1 : 0);
   return hipGetLastError() == hipSuccess ? 0 : -3;
-}
-
-int lu_f64_mw(int NP, const NewtonF64Args& a, int it, hipStream_t st) {
-  switch (NP) {
-#define RB_C(n) case n: return go_f64<n>(a, it, st);
-    RB_C(72) RB_C(80) RB_C(88) RB_C(96)
-#undef RB_C
-  }
-  return -5;
 }
 
 int lu_lp_mw(int NP, bool refine, const LpNewtonArgs& a, int it, hipStream_t st) {

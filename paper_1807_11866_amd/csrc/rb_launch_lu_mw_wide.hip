@@ -1,4 +1,6 @@
-// Instantiations of the multi-wavefront FP32 LU kernel for NP = 112..152 (multiples of 8).
+// Instantiations of the multi-wavefront FP32 LU kernel for NP = 112 and 120, and the
+// dispatcher over NP = 112..152 (multiples of 8; 128..152 in rb_launch_lu_mw_wide2.hip and
+// rb_launch_lu_mw_wide3.hip, so that the sizes compile in parallel).
 #include "rb_launch.hpp"
 
 namespace rb {
@@ -13,9 +15,11 @@ static int go_lp(bool refine, const LpNewtonArgs& a, int it, hipStream_t st) {
 }
 
 int lu_lp_mw_wide(int NP, bool refine, const LpNewtonArgs& a, int it, hipStream_t st) {
+  if (NP == 128 || NP == 136) return lu_lp_mw_wide2(NP, refine, a, it, st);
+  if (NP == 144 || NP == 152) return lu_lp_mw_wide3(NP, refine, a, it, st);
   switch (NP) {
 #define RB_C(n) case n: return go_lp<n>(refine, a, it, st);
-    RB_C(112) RB_C(120) RB_C(128) RB_C(136) RB_C(144) RB_C(152)
+    RB_C(112) RB_C(120)
 #undef RB_C
   }
   return -5;
