@@ -415,6 +415,32 @@ def test_status_codes_forced_from_host(R, c1):
     s.close()
 
 
+@pytest.mark.parametrize("N,prec", [(50, "F64"), (72, "F64"), (40, "F32"), (100, "F32")])
+def test_zero_pivot_status_every_solve(R, N, prec):
+    """Zero pivots in the one-wavefront solves (N = 50 FP64, N = 40 FP32) and the workgroup
+    solves (N = 72 FP64, N = 100 FP32): with the last column of every A_q zero, the first
+    Jacobian A(mu) meets an exact zero pivot at the last elimination step (requests 0 and
+    2); with theta^a = 0 it is zero and does so at the first (request 1). Every request
+    reports RB_ST_SINGULAR (2) after no completed iteration."""
+    rng = np.random.default_rng(N)
+    ts = _random_set(N, seed=N)
+    ts.A = ts.A.copy()
+    ts.A[:, :, N - 1] = 0.0
+    B = 3
+    ta = rng.uniform(0.1, 1.0, (B, ts.Q))
+    ta[1] = 0.0
+    tc = rng.uniform(-1.0, 1.0, (B, ts.Qc))
+    tf = rng.standard_normal((B, ts.Qf))
+    s = R.Solver(ts)
+    print(f"[zero pivot] N={N} {prec}", flush=True)
+    out = s.solve(dict(ta=_dev(ta), tc=_dev(tc), tf=_dev(tf)),
+                  precision=getattr(R, "RB_PREC_" + prec), refine_steps=1)
+    torch.cuda.synchronize()
+    assert list(out["status"].cpu().numpy()) == [2, 2, 2]
+    assert list(out["iters"].cpu().numpy()) == [0, 0, 0]
+    s.close()
+
+
 def test_call_level_errors(R, c1):
     s = R.Solver(c1)
     th = s.theta(_dev(np.array([[0.1, 200.0]])))
