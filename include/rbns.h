@@ -175,7 +175,8 @@ int rb_theta(rb_ctx *ctx, int set, int B, const double *mu, double *theta_a, dou
  * velonly, Section 2.2), the Jacobian assembled from the tensors (Section 3.5), at one basis
  * size N (1 <= N <= the set's N; per-request sizes: rb_solve_uneven). Device inputs: theta_a [B][Q], theta_c [B][Qc], and either theta_f [B][Qf] or
  * f_override [B][ldu] (right-hand sides replacing f(mu), e.g. for manufactured solutions);
- * u0 [B][ldu] initial iterates or NULL (zero: the first step is then the Stokes solve).
+ * u0 [B][ldu] initial iterates or NULL (zero: the first step is then the Stokes solve, whose
+ * Jacobian A(mu) is summed from the Q affine operators alone, at every precision).
  * Device outputs: u [B][ldu] (entries >= N are set to 0), iters [B] (Newton updates applied),
  * status [B] (RB_ST_*). ldu >= N is the row stride of u0 / f_override / u.
  * opts == NULL selects tol 1e-12, max_iter 10, RB_PREC_F64.
