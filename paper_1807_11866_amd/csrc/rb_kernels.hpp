@@ -164,7 +164,20 @@ __device__ __forceinline__ void stokes_tile(const NewtonF64Args& a, T* J, int64_
     double acc[kStokesReq];
 #pragma unroll
     for (int r = 0; r < kStokesReq; ++r) acc[r] = 0.0;
-    for (int q = 0; q < Q; ++q) {
+    int q = 0;
+    for (; q + 4 <= Q; q += 4) {           // one k-step (four operators) at a time
+      double x[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) x[j] = op[(q >> 2) * 64 + 16 * j];
+#pragma unroll
+      for (int r = 0; r < kStokesReq; ++r) {
+        const int64_t b = b0 + r < a.B ? b0 + r : a.B - 1;
+        const double* t = a.ta + b * Q + q;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[r] = fma(t[j], x[j], acc[r]);
+      }
+    }
+    for (; q < Q; ++q) {
       const double x = op[(q >> 2) * 64 + ((q & 3) << 4)];
 #pragma unroll
       for (int r = 0; r < kStokesReq; ++r) {
