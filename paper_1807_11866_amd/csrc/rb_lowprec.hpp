@@ -461,11 +461,11 @@ __global__ __launch_bounds__(kThreads) void lu_lp_kernel(LpNewtonArgs a, int it)
 }
 
 // NP > 64: one request per workgroup of W wavefronts (Gauss-Jordan over the workgroup),
-// same right-hand sides and stopping rules as lu_lp_kernel. Up to 104 unknowns the rows fit
-// in 168 registers, three wavefronts per SIMD (the solve is bound by its per-step latency
-// chain, so resident requests are what hides it).
+// same right-hand sides and stopping rules as lu_lp_kernel. Up to 72 unknowns the rows fit
+// in 128 registers (four wavefronts per SIMD), up to 104 in 168 (three); the solve is bound
+// by its per-step latency chain, so resident requests are what hides it.
 template <int NP, int W>
-__global__ __launch_bounds__(kWave * W) __attribute__((amdgpu_waves_per_eu(NP <= 104 ? 3 : 1)))
+__global__ __launch_bounds__(kWave * W) __attribute__((amdgpu_waves_per_eu(NP <= 72 ? 4 : (NP <= 104 ? 3 : 1))))
 void lu_lp_mw_kernel(LpNewtonArgs a, int it, int refine) {
   __shared__ GjShared<NP, W, float> sh;
   const int b = blockIdx.x;
